@@ -1,0 +1,258 @@
+"""Pins for the CPU oracle: it is checked against things other than itself.
+
+* brute force over the plain definition (oracle/bruteforce.py) on many tiny
+  seeded series -- MERLIN/DRAG must return exactly the top-k of P_m;
+* DRAG at a fixed r must return exactly {i : P_m(i) >= r} (Alg. 2's range
+  discord set, Sec. 2.1);
+* library routines: numpy mean/std for Eq. (4), numpy.corrcoef for the
+  Pearson form of Eq. (6);
+* closed forms and special cases: exact copies inside / just outside the
+  self-match zone, flat windows, distance bounds 0 <= ED <= 2 sqrt(m);
+* invariances: affine maps of T, time reversal;
+* the recurrences of Eq. (7)-(8) against direct two-pass statistics.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+from paper_2304_01660_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_cases(count=210):
+    rng = np.random.default_rng(12345)
+    kinds = ("rw", "noise", "ecg")
+    for c in range(count):
+        maxL = int(rng.integers(3, 21))
+        minL = int(rng.integers(3, maxL + 1))
+        minL = max(minL, maxL - 3)           # at most 4 lengths per case
+        n = int(rng.integers(max(60, 3 * maxL - 1), 601))
+        k = int((1, 3, 5)[c % 3])
+        kind = kinds[c % 3]
+        T = synth.small_random(1000 + c, n, kind)
+        yield c, T, minL, maxL, k
+
+
+def _check_topk(T, got_idx, got_nn, minL, maxL, k, rel=1e-12):
+    for m in range(minL, maxL + 1):
+        P, _ = bf.profile(T, m)
+        rows = slice((m - minL) * k, (m - minL + 1) * k)
+        gi = got_idx[rows]
+        gn = got_nn[rows]
+        exp = bf.topk(P, k)
+        np.testing.assert_allclose(gn, P[exp], rtol=rel, atol=1e-12)
+        for q in range(k):
+            if gi[q] != exp[q]:
+                # only a near-tie may reorder: the picked row's exact P must
+                # equal the expected one to the tolerance
+                assert abs(P[gi[q]] - P[exp[q]]) <= rel * max(1.0, P[exp[q]]), (m, q)
+        np.testing.assert_allclose(P[gi], gn, rtol=rel, atol=1e-12)
+
+
+def test_merlin_matches_bruteforce_on_tiny_series():
+    n_cases = 0
+    for c, T, minL, maxL, k in _tiny_cases():
+        o = oracle.merlin(T, minL, maxL, k)
+        _check_topk(T, o["idx"], o["nn"], minL, maxL, k)
+        # nearest neighbour index: a true non-self match at exactly that distance
+        for q in range(len(o["idx"])):
+            m = int(o["len"][q])
+            i, j = int(o["idx"][q]), int(o["nnidx"][q])
+            assert abs(i - j) >= m
+            d, jj = oracle.nn_row(T, m, i)
+            assert jj == j
+        n_cases += 1
+    assert n_cases >= 200
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_drag_returns_exact_range_discord_set(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(150, 500))
+    m = int(rng.integers(4, 25))
+    T = synth.small_random(seed, n, ("rw", "noise", "ecg")[seed % 3])
+    P, J = bf.profile(T, m)
+    for qtl in (0.0, 0.5, 0.9, 0.99, 1.0):
+        r = float(np.quantile(P, qtl)) * 0.999999
+        idx, nn, nnidx, _ = oracle.drag(T, m, r)
+        want = np.nonzero(P >= r)[0]
+        np.testing.assert_array_equal(idx, want)
+        np.testing.assert_allclose(nn, P[want], rtol=1e-12, atol=1e-12)
+        np.testing.assert_array_equal(nnidx, J[want])
+    # r above every distance: nothing survives; r <= 0: everything survives
+    idx, _, _, _ = oracle.drag(T, m, 2.0 * math.sqrt(m) * 1.0001)
+    assert idx.size == 0
+    idx, nn, _, _ = oracle.drag(T, m, 0.0)
+    np.testing.assert_array_equal(idx, np.arange(n - m + 1))
+    np.testing.assert_allclose(nn, P, rtol=1e-12, atol=1e-12)
+    idx, _, _, _ = oracle.drag(T, m, -1.0)
+    assert idx.size == n - m + 1
+
+
+def test_window_stats_match_numpy():
+    T = synth.small_random(7, 3000, "rw") * 37.0 + 1e4
+    for m in (3, 17, 128):
+        mu, sd = oracle.window_stats(T, m)
+        W = np.lib.stride_tricks.sliding_window_view(T, m)
+        np.testing.assert_allclose(mu, W.mean(axis=1), rtol=1e-14)
+        np.testing.assert_allclose(sd, W.std(axis=1), rtol=1e-9)
+
+
+def test_recurrences_eq7_eq8_match_two_pass():
+    """Eq. (7)-(8) (proved in the Appendix) reproduce the direct statistics."""
+    T = synth.small_random(8, 5000, "rw")
+    minL, maxL = 16, 80
+    mu, sd = oracle.window_stats(T, minL)
+    var = sd ** 2
+    for m in range(minL, maxL):
+        N1 = T.shape[0] - m          # windows of length m+1
+        t = T[m:m + N1]              # t_{i+m}
+        mu_n = (m * mu[:N1] + t) / (m + 1)
+        var_n = m / (m + 1) * (var[:N1] + (mu[:N1] - t) ** 2 / (m + 1))
+        mu, var = mu_n, var_n
+        mu2, sd2 = oracle.window_stats(T, m + 1)
+        scale = np.abs(T).max()
+        np.testing.assert_allclose(mu, mu2, rtol=1e-12, atol=1e-13 * scale)
+        np.testing.assert_allclose(np.sqrt(var), sd2, rtol=1e-10)
+
+
+def test_pearson_identity_eq6():
+    """ED^2 of z-normalised windows = 2m(1 - rho), rho from numpy.corrcoef."""
+    T = synth.small_random(9, 800, "rw")
+    rng = np.random.default_rng(0)
+    for m in (5, 32, 100):
+        N = T.shape[0] - m + 1
+        for _ in range(40):
+            i = int(rng.integers(0, N))
+            d, j = oracle.nn_row(T, m, i)
+            rho = np.corrcoef(T[i:i + m], T[j:j + m])[0, 1]
+            assert abs(d * d - 2 * m * (1 - rho)) <= 1e-10 * (1 + d * d)
+
+
+def test_distance_bounds():
+    for seed in range(6):
+        T = synth.small_random(20 + seed, 400, ("rw", "noise", "ecg")[seed % 3])
+        for m in (3, 10, 40):
+            P, _ = bf.profile(T, m)
+            assert np.all(P >= 0) and np.all(P <= 2 * math.sqrt(m) + 1e-12)
+            o = oracle.merlin(T, m, m, 3)
+            assert np.all(o["nn"] >= 0) and np.all(o["nn"] <= 2 * math.sqrt(m) + 1e-12)
+
+
+def test_self_match_exclusion_boundary():
+    """A copy at offset m-1 is a self match (ignored); at offset m it is not."""
+    rng = np.random.default_rng(3)
+    m = 12
+    for off, expect_zero in ((m - 1, False), (m, True)):
+        T = rng.standard_normal(300)
+        i = 100
+        T[i + off:i + off + m] = T[i:i + m] * 3.0 + 5.0     # affine copy = same z-norm window
+        d, j = oracle.nn_row(T, m, i)
+        P, J = bf.profile(T, m)
+        assert abs(P[i] - d) <= 1e-12
+        if expect_zero:
+            assert d < 1e-6 and j == i + off
+        else:
+            assert d > 0.1
+
+
+def test_flat_windows_convention():
+    rng = np.random.default_rng(4)
+    T = rng.standard_normal(400)
+    T[50:90] = 2.5            # flat run long enough for several flat windows
+    T[250:262] = -1.0         # a second flat run
+    m = 10
+    P, J = bf.profile(T, m)
+    idx, nn, nnidx, _ = oracle.drag(T, m, 0.0)
+    np.testing.assert_allclose(nn, P, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(nnidx, J)
+    # window 50 is flat and has a flat non-self match (window 80 or 250)
+    assert P[50] == 0.0
+
+
+def test_affine_and_reversal_invariance():
+    T = synth.small_random(30, 500, "rw")
+    minL, maxL, k = 8, 11, 3
+    base = oracle.merlin(T, minL, maxL, k)
+    aff = oracle.merlin(-2.5 * T + 7.0, minL, maxL, k)
+    np.testing.assert_array_equal(base["idx"], aff["idx"])
+    np.testing.assert_allclose(base["nn"], aff["nn"], rtol=1e-9)
+    for m in (minL, maxL):
+        P, _ = bf.profile(T, m)
+        Pr, _ = bf.profile(T[::-1].copy(), m)
+        np.testing.assert_allclose(Pr[::-1], P, rtol=1e-10, atol=1e-12)
+
+
+def test_r_schedule_does_not_change_result():
+    """DRAG at r = exact k-th value, at r = 0 and MERLIN's schedule agree."""
+    T = synth.small_random(31, 700, "ecg")
+    m, k = 20, 5
+    P, _ = bf.profile(T, m)
+    kth = float(np.sort(P)[::-1][k - 1])
+    a = oracle.merlin(T, m, m, k)
+    for r in (kth, 0.0, 0.5 * kth):
+        idx, nn, _, _ = oracle.drag(T, m, r)
+        order = np.lexsort((idx, -nn))[:k]
+        np.testing.assert_array_equal(idx[order], a["idx"])
+        np.testing.assert_allclose(nn[order], a["nn"], rtol=1e-12)
+
+
+def test_gradient_matches_finite_differences_and_invariants():
+    T = synth.small_random(40, 400, "rw")
+    m = 16
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        i = int(rng.integers(0, T.shape[0] - m + 1))
+        d, j = oracle.nn_row(T, m, i)
+        g = oracle.nn_grad(T, m, i, j)
+
+        def dist_fixed_j(S):
+            x = S[i:i + m]
+            y = S[j:j + m]
+            xh = (x - x.mean()) / x.std()
+            yh = (y - y.mean()) / y.std()
+            return math.sqrt(((xh - yh) ** 2).sum())
+
+        h = 1e-6
+        for p in list(range(i, i + m)) + list(range(j, j + m)):
+            Sp = T.copy(); Sp[p] += h
+            Sm = T.copy(); Sm[p] -= h
+            fd = (dist_fixed_j(Sp) - dist_fixed_j(Sm)) / (2 * h)
+            assert abs(fd - g[p]) <= 1e-6 + 1e-5 * abs(g[p])
+        # zero outside the two supports
+        mask = np.ones(T.shape[0], bool)
+        mask[i:i + m] = False
+        mask[j:j + m] = False
+        assert np.all(g[mask] == 0.0)
+        # shift invariance and degree-0 homogeneity of each window's part
+        for a0 in (i, j):
+            part = g[a0:a0 + m]
+            assert abs(part.sum()) <= 1e-10
+            assert abs((part * T[a0:a0 + m]).sum()) <= 1e-8 * (1 + np.abs(T).max())
+        # closed form through the Pearson correlation (Eq. (6)):
+        # d P / d x_k = (rho * xh_k - yh_k) / (sigma_x * P)
+        x, y = T[i:i + m], T[j:j + m]
+        xh = (x - x.mean()) / x.std()
+        yh = (y - y.mean()) / y.std()
+        rho = float(np.corrcoef(x, y)[0, 1])
+        np.testing.assert_allclose(g[i:i + m], (rho * xh - yh) / (x.std() * d), rtol=1e-8,
+                                   atol=1e-12)
+
+
+def test_config1_golden_is_regenerable_and_matches_bruteforce():
+    path = os.path.join(GOLD, "c1_rw2k_m32-40_k1_fp64.json")
+    with open(path) as f:
+        g = json.load(f)
+    w = synth.config1()
+    assert synth.sha256(w.T) == g["sha256"]
+    b = bf.discords(w.T, w.minL, w.maxL, w.k)
+    np.testing.assert_array_equal(b["idx"], np.array(g["idx"]))
+    np.testing.assert_allclose(b["nn"], np.array(g["nn"]), rtol=1e-12)
+    np.testing.assert_array_equal(b["nnidx"], np.array(g["nnidx"]))
