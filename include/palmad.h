@@ -1,0 +1,183 @@
+/*
+ * palmad.h -- C ABI of the MI355X (gfx950) range-discord search library.
+ *
+ * The library finds, for every subsequence length m in [minL, maxL], the
+ * top-k discords of a time series: the subsequences whose distance to their
+ * nearest non-self match is largest (Sec. 2.1, Eq. (1)-(5)), by the method of
+ * the paper: per-length statistics updated by recurrence (Sec. 3.1.1,
+ * Eq. (7)-(8)), candidate selection and refinement passes against a range r
+ * (Sec. 3.2-3.3, after the serial DRAG of Alg. 2), and MERLIN's adaptive
+ * choice of r over the lengths (Alg. 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Indices are 0-based.  Subsequence i of length m covers T[i .. i+m-1];
+ *     N(m) = n - m + 1.  Two subsequences are a non-self match iff
+ *     |i - j| >= m.
+ *   - Distances are z-normalised Euclidean distances (population sigma) in
+ *     ED units, not squared.  A flat window (sigma <= 1e-12 * max(1, sigma
+ *     of the whole series)) is at distance 0 from another flat window and
+ *     sqrt(2m) from any other window.
+ *   - Output row q = (m - minL) * k + rank; rank 0 has the largest nnDist;
+ *     equal nnDist values are ordered by smaller index; a nearest-neighbour
+ *     tie reports the smaller neighbour index.
+ *   - Pointers documented as "device" must point to memory of the context's
+ *     device; the library never frees or retains them.  Calls are issued on
+ *     the HIP stream given to the call and return after the result is
+ *     complete (the adaptive r loop reads one flag per range search).
+ *   - Every function returns a palmad_status.  Arguments are validated on
+ *     the host before any device work; on error nothing is written to the
+ *     outputs and palmad_last_error() describes the problem.  No C++
+ *     exception crosses this interface.
+ *   - One context per host thread at a time.
+ */
+#ifndef PALMAD_H
+#define PALMAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PALMAD_OK = 0,
+    PALMAD_EINVAL = -1,       /* invalid argument (null pointer, bad range, ...) */
+    PALMAD_ENONFINITE = -2,   /* the series holds NaN or Inf */
+    PALMAD_EWORKSPACE = -3,   /* workspace smaller than palmad_workspace_size() */
+    PALMAD_EDEVICE = -4,      /* a HIP call failed */
+    PALMAD_ENOMEM = -5,       /* host allocation failed */
+    PALMAD_EUNSUPPORTED = -6  /* valid request outside what this build supports */
+} palmad_status;
+
+/* Options; a zero-initialised struct selects the defaults. */
+typedef struct {
+    int32_t dist_bits;     /* 32: FP32 selection sweep (statistics, refinement and
+                              reported distances stay FP64); 64: FP64 throughout.
+                              0 = 32. */
+    float guard;           /* correlation guard band of the FP32 selection sweep:
+                              a pair prunes only if its FP32 correlation exceeds the
+                              threshold by more than this.  <= 0 = 1e-4. */
+    int32_t near_cols;     /* columns scanned by the first selection pass of a row
+                              tile before the remaining columns are split across
+                              workgroups; 0 = 2048. */
+    int32_t chunk_cols;    /* columns per work item of the split passes; 0 = 1024. */
+    uint32_t flags;        /* PALMAD_FLAG_* bits */
+    int32_t reserved[7];   /* must be zero */
+} palmad_options;
+
+/* Record HIP events around the sweep kernels and report their summed device
+   time per kernel class in palmad_stats (adds two event records per timed
+   launch). */
+#define PALMAD_FLAG_TIME_KERNELS 1u
+
+/* Kernel classes of palmad_stats.kernel_* (one entry each). */
+enum {
+    PALMAD_KERNEL_SELECT_NEAR = 0, /* first selection pass of every row tile */
+    PALMAD_KERNEL_SELECT_FAR = 1,  /* split selection pass over the remaining columns */
+    PALMAD_KERNEL_REFINE = 2,      /* refinement pass (exact FP64 nearest neighbour) */
+    PALMAD_KERNEL_POLISH = 3,      /* direct FP64 distances of the top candidates */
+    PALMAD_KERNEL_CLASSES = 4
+};
+
+/* Per-call counters (host struct, filled when the call returns). */
+typedef struct {
+    uint64_t evals_select;   /* pair correlations evaluated by selection passes */
+    uint64_t evals_refine;   /* pair correlations evaluated by refinement passes */
+    uint64_t evals_polish;   /* pair distances evaluated by the exact FP64 pass */
+    uint64_t range_searches; /* selection+refinement rounds (DRAG calls), all lengths */
+    uint64_t survivors;      /* range discords summed over the successful rounds */
+    double seconds;          /* host wall time of the call */
+    uint64_t kernel_evals[PALMAD_KERNEL_CLASSES];    /* pair evaluations per class */
+    uint64_t kernel_launches[PALMAD_KERNEL_CLASSES]; /* launches per class */
+    double kernel_ms[PALMAD_KERNEL_CLASSES];         /* device time per class (flag set) */
+} palmad_stats;
+
+typedef struct palmad_ctx palmad_ctx;
+
+/* Library version string (static storage). */
+const char* palmad_version(void);
+
+/* Message for the last error on this context (or of the last failed
+   palmad_create / argument check when ctx is NULL).  Static or
+   context-owned storage; valid until the next call on the context. */
+const char* palmad_last_error(const palmad_ctx* ctx);
+
+/* Create a context bound to HIP device `device`.  *out receives the
+   context; destroy it with palmad_destroy().  Allocates a few hundred bytes
+   of device and pinned host memory for control state. */
+int palmad_create(palmad_ctx** out, int device);
+
+/* Destroy a context (NULL is ignored).  Waits for the context's work. */
+void palmad_destroy(palmad_ctx* ctx);
+
+/*
+ * Bytes of device workspace palmad_discords() needs for a series of length
+ * n, lengths [minL, maxL] and top-k.  Pure host computation (no device, no
+ * context).  Returns PALMAD_EINVAL for arguments palmad_discords() would
+ * reject: minL < 3, maxL < minL, n < 3*maxL - 1 (so that every subsequence
+ * has a non-self match), k < 1, k > 64 or k > n - maxL + 1.
+ */
+int palmad_workspace_size(int64_t n, int32_t minL, int32_t maxL, int32_t k,
+                          const palmad_options* opts, size_t* bytes);
+
+/*
+ * Top-k discords of every length in [minL, maxL] (MERLIN over the lengths,
+ * Alg. 1; each range search is a selection pass and a refinement pass,
+ * Sec. 3.2-3.3).
+ *
+ *   T          device, float64[n]: the series (read only).
+ *   workspace  device, >= palmad_workspace_size() bytes, 256-byte aligned;
+ *              scratch owned by the caller, contents undefined on return.
+ *   idx        device, int64[L*k]: start index of each discord.
+ *   len        device, int32[L*k]: its length m.
+ *   nn_dist    device, float64[L*k]: distance to its nearest non-self match.
+ *   nn_idx     device, int64[L*k]: index of that nearest non-self match.
+ *   count      device, int32[L]: number of range discords (subsequences with
+ *              nnDist >= r) found by the successful range search of each
+ *              length; always >= k.
+ *   stats      host, optional (NULL): counters of this call.
+ *   stream     HIP stream (hipStream_t) or NULL for the null stream.
+ * with L = maxL - minL + 1.
+ */
+int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t maxL,
+                    int32_t k, const palmad_options* opts, void* workspace, size_t ws_bytes,
+                    int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx, int32_t* count,
+                    palmad_stats* stats, void* stream);
+
+/*
+ * One range search at a single length m and range r (the DRAG problem of
+ * Alg. 2 as parallelised in Sec. 3.2-3.3): every subsequence whose nearest
+ * non-self match is at distance >= r, with that distance.  r <= 0 returns
+ * every subsequence (the exact nearest-neighbour distance of all of them).
+ *
+ *   T          device, float64[n].
+ *   workspace  device, >= palmad_workspace_size(n, m, m, 1, opts) bytes.
+ *   alive      device, uint64[ceil(N/64)]: bit i%64 of word i/64 is set iff
+ *              subsequence i is a range discord (N = n - m + 1).
+ *   nn_dist    device, float64[N]: exact nnDist where the bit is set,
+ *              unspecified elsewhere.
+ *   count      host: number of range discords.
+ */
+int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m, double r,
+                          const palmad_options* opts, void* workspace, size_t ws_bytes,
+                          uint64_t* alive, double* nn_dist, int64_t* count, palmad_stats* stats,
+                          void* stream);
+
+/*
+ * Mean and population standard deviation of every window of length m, as
+ * the search computes them: direct two-pass sums at length minL (Eq. (4)),
+ * then the recurrences of Eq. (7)-(8) for minL+1 .. m.
+ *
+ *   T      device, float64[n];  mu, sigma: device, float64[n - m + 1].
+ *   workspace: device, >= palmad_workspace_size(n, minL, m, 1, NULL) bytes.
+ * Requires 3 <= minL <= m and n >= 3*m - 1.
+ */
+int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
+                        void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PALMAD_H */

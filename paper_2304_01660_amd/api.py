@@ -1,0 +1,150 @@
+"""Python API over the C ABI: torch tensors in, torch tensors out.
+
+Torch supplies device memory (inputs, outputs, workspace) and the current
+HIP stream; every step of the search runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+
+_ctx_lock = threading.Lock()
+_ctxs = {}
+
+
+def context(device: int):
+    """The library context of a device (created once per process)."""
+    with _ctx_lock:
+        c = _ctxs.get(device)
+        if c is None:
+            p = ctypes.c_void_p()
+            _lib.check(_lib.lib().palmad_create(ctypes.byref(p), int(device)))
+            c = p
+            _ctxs[device] = c
+        return c
+
+
+def workspace_size(n: int, minL: int, maxL: int, k: int, **opts) -> int:
+    o = _lib.make_options(**opts)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_workspace_size(int(n), int(minL), int(maxL), int(k),
+                                                ctypes.byref(o), ctypes.byref(nbytes)))
+    return int(nbytes.value)
+
+
+def _series(T: torch.Tensor) -> torch.Tensor:
+    if not isinstance(T, torch.Tensor):
+        raise TypeError("T must be a torch tensor on a GPU")
+    if T.device.type != "cuda":
+        raise ValueError("T must live on a GPU device")
+    if T.dim() != 1:
+        raise ValueError("T must be one-dimensional")
+    return T.to(torch.float64).contiguous()
+
+
+def _stream(dev) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _workspace(nbytes: int, dev) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte aligned blocks
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
+             guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0, workspace=None,
+             return_stats: bool = False, time_kernels: bool = False):
+    """Top-k discords of every length in [minL, maxL].
+
+    Returns a dict of device tensors: idx int64[L*k], len int32[L*k],
+    nn_dist float64[L*k], nn_idx int64[L*k], count int32[L]; row
+    (m - minL) * k + rank.  With ``return_stats`` also the call's counters.
+    """
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    L = maxL - minL + 1
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels)
+    nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
+                            near_cols=near_cols, chunk_cols=chunk_cols)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace has {ws.numel()} bytes, needs {nbytes}")
+    out = {
+        "idx": torch.empty(L * k, dtype=torch.int64, device=dev),
+        "len": torch.empty(L * k, dtype=torch.int32, device=dev),
+        "nn_dist": torch.empty(L * k, dtype=torch.float64, device=dev),
+        "nn_idx": torch.empty(L * k, dtype=torch.int64, device=dev),
+        "count": torch.empty(L, dtype=torch.int32, device=dev),
+    }
+    st = _lib.Stats()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_discords(
+        ctx, ctypes.c_void_p(T.data_ptr()), n, minL, maxL, k, ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out["idx"].data_ptr()),
+        ctypes.c_void_p(out["len"].data_ptr()), ctypes.c_void_p(out["nn_dist"].data_ptr()),
+        ctypes.c_void_p(out["nn_idx"].data_ptr()), ctypes.c_void_p(out["count"].data_ptr()),
+        ctypes.byref(st), _stream(dev))
+    _lib.check(rc, ctx)
+    if return_stats:
+        out["stats"] = st.as_dict()
+    return out
+
+
+def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, guard: float = 0.0,
+                   near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False):
+    """All subsequences of length m whose nearest non-self match is >= r away.
+
+    Returns (mask bool[N] on the device, nn_dist float64[N] valid where mask,
+    count); with ``return_stats`` also the counters.
+    """
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    N = n - m + 1
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols)
+    nbytes = workspace_size(n, m, m, 1, dist_bits=dist_bits, guard=guard, near_cols=near_cols,
+                            chunk_cols=chunk_cols)
+    ws = _workspace(nbytes, dev)
+    words = torch.empty((N + 63) // 64, dtype=torch.int64, device=dev)
+    nn = torch.empty(N, dtype=torch.float64, device=dev)
+    cnt = ctypes.c_int64(0)
+    st = _lib.Stats()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_range_discords(
+        ctx, ctypes.c_void_p(T.data_ptr()), n, m, float(r), ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(words.data_ptr()),
+        ctypes.c_void_p(nn.data_ptr()), ctypes.byref(cnt), ctypes.byref(st), _stream(dev))
+    _lib.check(rc, ctx)
+    bits = torch.arange(64, device=dev, dtype=torch.int64)
+    mask = ((words[:, None] >> bits[None, :]) & 1).reshape(-1)[:N].bool()
+    res = (mask, nn, int(cnt.value))
+    if return_stats:
+        return res + (st.as_dict(),)
+    return res
+
+
+def window_stats(T: torch.Tensor, minL: int, m: int):
+    """(mu, sigma) of every window of length m, from Eq. (4) at minL then Eq. (7)-(8)."""
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    N = n - m + 1
+    nbytes = workspace_size(n, minL, m, 1)
+    ws = _workspace(nbytes, dev)
+    mu = torch.empty(N, dtype=torch.float64, device=dev)
+    sg = torch.empty(N, dtype=torch.float64, device=dev)
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_window_stats(ctx, ctypes.c_void_p(T.data_ptr()), n, minL, m,
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        ctypes.c_void_p(mu.data_ptr()),
+                                        ctypes.c_void_p(sg.data_ptr()), _stream(dev))
+    _lib.check(rc, ctx)
+    return mu, sg

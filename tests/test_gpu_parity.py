@@ -1,0 +1,247 @@
+"""GPU parity: the HIP library against the CPU oracle (oracle/), through the C ABI.
+
+Every case is seeded and synthetic; sizes span several row tiles with ragged
+tails.  Floating-point tolerance: the library evaluates distances in the
+Pearson form ED^2 = 2m(1 - rho) in FP64 (Eq. (6)), the oracle on explicitly
+z-normalised windows (Eq. (4)-(5)).  With rho carrying an absolute error of
+about 1e-14, ED^2 may differ by 2m * 1e-12 absolutely (this dominates only
+for near-identical windows) plus 1e-9 relatively.  Indices must be
+identical, except that a near tie may reorder: a reported index g is
+accepted in place of the oracle's e when the oracle's P_m(g) equals P_m(e)
+within that tolerance.
+"""
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+from paper_2304_01660_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+REL = 1e-9
+RHO_ABS = 1e-12
+
+
+def close_ed(a, b, m, rel=REL):
+    """|a^2 - b^2| within 2m*RHO_ABS + rel*b^2 (elementwise, numpy)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a * a - b * b) <= 2.0 * m * RHO_ABS + 2.0 * rel * b * b + 1e-300
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def _api():
+    from paper_2304_01660_amd import api
+    return api
+
+
+def _check_against_profiles(T, out, minL, maxL, k, rel=REL):
+    idx = out["idx"].cpu().numpy()
+    ln = out["len"].cpu().numpy()
+    nn = out["nn_dist"].cpu().numpy()
+    nnj = out["nn_idx"].cpu().numpy()
+    cnt = out["count"].cpu().numpy()
+    assert np.all(cnt >= k)
+    for m in range(minL, maxL + 1):
+        P, J = bf.profile(T, m)
+        rows = slice((m - minL) * k, (m - minL + 1) * k)
+        exp = bf.topk(P, k)
+        assert np.all(ln[rows] == m)
+        for q in range(k):
+            g, e = int(idx[rows][q]), int(exp[q])
+            if g != e:
+                assert close_ed(P[g], P[e], m, rel), (m, q, g, e, P[g], P[e])
+            assert close_ed(nn[rows][q], P[g], m, rel), (m, q, nn[rows][q], P[g])
+            j = int(nnj[rows][q])
+            assert abs(j - g) >= m
+            # the reported neighbour realises the nearest distance
+            Zg = (T[g:g + m] - T[g:g + m].mean()) / T[g:g + m].std()
+            Zj = (T[j:j + m] - T[j:j + m].mean()) / T[j:j + m].std()
+            d = math.sqrt(((Zg - Zj) ** 2).sum())
+            assert abs(d - P[g]) <= 1e-7 * max(1.0, P[g]), (m, q, j, J[g], d, P[g])
+
+
+def test_window_stats_match_oracle():
+    dev = _dev()
+    api = _api()
+    for n, minL, m in ((100, 8, 8), (1003, 8, 9), (5000, 8, 40), (5000, 16, 140)):
+        T = synth.small_random(77 + n, n, "rw") * 3.0 + 250.0
+        _say("window_stats", n, minL, m)
+        mu, sg = api.window_stats(torch.from_numpy(T).to(dev), minL, m)
+        mu0, sg0 = oracle.window_stats(T, m)
+        scale = np.abs(T).max()
+        np.testing.assert_allclose(mu.cpu().numpy(), mu0, rtol=1e-12, atol=1e-13 * scale)
+        np.testing.assert_allclose(sg.cpu().numpy(), sg0, rtol=1e-9)
+
+
+@pytest.mark.parametrize("dist_bits", [64, 32])
+@pytest.mark.parametrize("seed,n,m", [(1, 300, 8), (2, 1000, 25), (3, 2333, 64), (4, 1777, 3),
+                                      (5, 4100, 100)])
+def test_range_search_matches_oracle_drag(dist_bits, seed, n, m):
+    dev = _dev()
+    api = _api()
+    T = synth.small_random(seed, n, ("rw", "noise", "ecg")[seed % 3])
+    P, J = bf.profile(T, m)
+    for qtl in (0.0, 0.5, 0.95, 0.999, 1.0):
+        r = float(np.quantile(P, qtl)) * (1 - 1e-7)
+        _say("range", dist_bits, seed, n, m, qtl, r)
+        mask, nn, cnt = api.range_discords(torch.from_numpy(T).to(dev), m, r, dist_bits=dist_bits)
+        mask = mask.cpu().numpy()
+        nn = nn.cpu().numpy()
+        want = P >= r
+        far = ~close_ed(P, np.full_like(P, r), m, 1e-9)
+        np.testing.assert_array_equal(mask[far], want[far])
+        assert cnt == int(mask.sum())
+        assert np.all(close_ed(nn[mask], P[mask], m))
+    for r in (0.0, -1.0):
+        _say("range", dist_bits, seed, n, m, "r", r)
+        mask, nn, cnt = api.range_discords(torch.from_numpy(T).to(dev), m, r, dist_bits=dist_bits)
+        assert cnt == n - m + 1 and bool(mask.all())
+        assert np.all(close_ed(nn.cpu().numpy(), P, m))
+    r = 2.0 * math.sqrt(m) * 1.001
+    _say("range", dist_bits, seed, n, m, "r", r)
+    mask, nn, cnt = api.range_discords(torch.from_numpy(T).to(dev), m, r, dist_bits=dist_bits)
+    assert cnt == 0
+
+
+def _tiny_cases():
+    rng = np.random.default_rng(2025)
+    for c in range(24):
+        kind = ("rw", "noise", "ecg")[c % 3]
+        maxL = int(rng.integers(6, 70))
+        minL = max(3, maxL - int(rng.integers(0, 5)))
+        n = int(rng.integers(max(3 * maxL, 200), 3200))
+        k = (1, 3, 5, 2)[c % 4]
+        yield c, kind, n, minL, maxL, k
+
+
+@pytest.mark.parametrize("dist_bits", [64, 32])
+def test_discords_match_bruteforce_tiny(dist_bits):
+    dev = _dev()
+    api = _api()
+    for c, kind, n, minL, maxL, k in _tiny_cases():
+        T = synth.small_random(5000 + c, n, kind)
+        _say("tiny", dist_bits, c, kind, n, minL, maxL, k)
+        out = api.discords(torch.from_numpy(T).to(dev), minL, maxL, k, dist_bits=dist_bits)
+        _check_against_profiles(T, out, minL, maxL, k)
+
+
+def test_config1_matches_golden():
+    dev = _dev()
+    api = _api()
+    w = synth.config1()
+    g = json.load(open(os.path.join(GOLD, "c1_rw2k_m32-40_k1_fp64.json")))
+    assert synth.sha256(w.T) == g["sha256"]
+    _say("config1")
+    out = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, w.k, dist_bits=64)
+    np.testing.assert_array_equal(out["idx"].cpu().numpy(), np.array(g["idx"]))
+    np.testing.assert_allclose(out["nn_dist"].cpu().numpy(), np.array(g["nn"]), rtol=1e-9)
+    np.testing.assert_array_equal(out["nn_idx"].cpu().numpy(), np.array(g["nnidx"]))
+
+
+def _golden(tag):
+    for f in sorted(os.listdir(GOLD)):
+        if f.startswith(tag + "_") and f.endswith(".json"):
+            return json.load(open(os.path.join(GOLD, f)))
+    return None
+
+
+def _match_golden(T, out, g, rel=1e-9):
+    idx = out["idx"].cpu().numpy()
+    nn = out["nn_dist"].cpu().numpy()
+    gi = np.array(g["idx"])
+    gn = np.array(g["nn"])
+    k = g["k"]
+    for q in range(len(gi)):
+        m = g["minL"] + q // k
+        if idx[q] != gi[q]:
+            # near tie: the oracle's exact distance of the reported row must match
+            d, _ = oracle.nn_row(T, m, int(idx[q]))
+            assert abs(d - gn[q]) <= rel * max(1.0, gn[q]), (q, idx[q], gi[q], d, gn[q])
+    np.testing.assert_allclose(nn, gn, rtol=rel)
+
+
+def test_config2_matches_golden():
+    g = _golden("c2")
+    if g is None:
+        pytest.skip("config-2 golden not generated")
+    dev = _dev()
+    api = _api()
+    w = synth.config2()
+    assert synth.sha256(w.T) == g["sha256"]
+    _say("config2")
+    out = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, w.k)
+    _match_golden(w.T, out, g)
+
+
+def test_edge_cases():
+    dev = _dev()
+    api = _api()
+    rng = np.random.default_rng(99)
+    # minimum admissible length n = 3*maxL - 1, single length
+    T = rng.standard_normal(3 * 20 - 1)
+    _say("edge n=3maxL-1")
+    out = api.discords(torch.from_numpy(T).to(dev), 20, 20, 2)
+    _check_against_profiles(T, out, 20, 20, 2)
+    # m = 3, k at the supported maximum
+    T = synth.small_random(11, 900, "noise")
+    _say("edge m=3 k=64")
+    out = api.discords(torch.from_numpy(T).to(dev), 3, 4, 64)
+    _check_against_profiles(T, out, 3, 4, 64)
+    # a large constant offset (cancellation in raw dot products)
+    T = synth.small_random(12, 1500, "rw") + 1e6
+    _say("edge offset 1e6")
+    out = api.discords(torch.from_numpy(T).to(dev), 30, 33, 3)
+    _check_against_profiles(T, out, 30, 33, 3, rel=1e-7)
+    # flat windows
+    T = rng.standard_normal(1200)
+    T[300:380] = 2.0
+    T[900:915] = -1.0
+    _say("edge flat")
+    mask, nn, cnt = api.range_discords(torch.from_numpy(T).to(dev), 10, 0.0)
+    P, _ = bf.profile(T, 10)
+    assert np.all(close_ed(nn.cpu().numpy(), P, 10))
+    out = api.discords(torch.from_numpy(T).to(dev), 10, 12, 3)
+    _check_against_profiles(T, out, 10, 12, 3)
+
+
+def test_deterministic():
+    dev = _dev()
+    api = _api()
+    T = torch.from_numpy(synth.small_random(13, 20000, "rw")).to(dev)
+    _say("determinism")
+    a = api.discords(T, 40, 45, 3)
+    b = api.discords(T, 40, 45, 3)
+    for key in ("idx", "nn_dist", "nn_idx", "count"):
+        assert torch.equal(a[key], b[key]), key
+
+
+def test_nonfinite_input_is_rejected():
+    dev = _dev()
+    api = _api()
+    from paper_2304_01660_amd._lib import PalmadError
+    T = synth.small_random(14, 500, "rw")
+    T[123] = np.nan
+    _say("nonfinite")
+    with pytest.raises(PalmadError) as ei:
+        api.discords(torch.from_numpy(T).to(dev), 10, 12, 1)
+    assert ei.value.code == -2
