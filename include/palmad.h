@@ -59,11 +59,16 @@ typedef struct {
                               a pair prunes only if its FP32 correlation exceeds the
                               threshold by more than this.  <= 0 = 1e-4. */
     int32_t near_cols;     /* columns scanned by the first selection pass of a row
-                              tile before the remaining columns are split across
-                              workgroups; 0 = 2048. */
-    int32_t chunk_cols;    /* columns per work item of the split passes; 0 = 1024. */
+                              tile (in chunks of chunk_cols run concurrently) before
+                              the remaining columns go to the queued pass; 0 = 2048. */
+    int32_t chunk_cols;    /* columns per work item of the sweeps; 0 = 1024. */
     uint32_t flags;        /* PALMAD_FLAG_* bits */
-    int32_t reserved[7];   /* must be zero */
+    int32_t rows_near;     /* row-tile height of the first selection pass: 128, 256 or
+                              512; 0 = 512 (FP32) / 256 (FP64). */
+    int32_t rows_far;      /* row-tile height of the split selection pass; 0 = as near. */
+    int32_t rows_refine;   /* row-tile height of the refinement pass; 0 = 128. */
+    int32_t far_grid;      /* workgroups of the split passes (1..65536); 0 = 2048. */
+    int32_t reserved[3];   /* must be zero */
 } palmad_options;
 
 /* Record HIP events around the sweep kernels and report their summed device
@@ -116,7 +121,8 @@ void palmad_destroy(palmad_ctx* ctx);
  * n, lengths [minL, maxL] and top-k.  Pure host computation (no device, no
  * context).  Returns PALMAD_EINVAL for arguments palmad_discords() would
  * reject: minL < 3, maxL < minL, n < 3*maxL - 1 (so that every subsequence
- * has a non-self match), k < 1, k > 64 or k > n - maxL + 1.
+ * has a non-self match), k < 1 or k > n - maxL + 1; PALMAD_EUNSUPPORTED for
+ * k > 64 or maxL > 3000.
  */
 int palmad_workspace_size(int64_t n, int32_t minL, int32_t maxL, int32_t k,
                           const palmad_options* opts, size_t* bytes);

@@ -32,7 +32,11 @@ class Options(ctypes.Structure):
         ("near_cols", ctypes.c_int32),
         ("chunk_cols", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("rows_near", ctypes.c_int32),
+        ("rows_far", ctypes.c_int32),
+        ("rows_refine", ctypes.c_int32),
+        ("far_grid", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -114,8 +118,13 @@ def check(rc: int, ctx=None):
         raise PalmadError(rc, msg.decode() if msg else "")
 
 
-def make_options(dist_bits=0, guard=0.0, near_cols=0, chunk_cols=0, time_kernels=False) -> Options:
+def make_options(dist_bits=0, guard=0.0, near_cols=0, chunk_cols=0, time_kernels=False,
+                 rows_near=0, rows_far=0, rows_refine=0, far_grid=0) -> Options:
     o = Options()
+    o.far_grid = int(far_grid)
+    o.rows_near = int(rows_near)
+    o.rows_far = int(rows_far)
+    o.rows_refine = int(rows_refine)
     o.dist_bits = int(dist_bits)
     o.guard = float(guard)
     o.near_cols = int(near_cols)

@@ -60,7 +60,8 @@ def _workspace(nbytes: int, dev) -> torch.Tensor:
 
 def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
              guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0, workspace=None,
-             return_stats: bool = False, time_kernels: bool = False):
+             return_stats: bool = False, time_kernels: bool = False, rows_near: int = 0,
+             rows_far: int = 0, rows_refine: int = 0, far_grid: int = 0):
     """Top-k discords of every length in [minL, maxL].
 
     Returns a dict of device tensors: idx int64[L*k], len int32[L*k],
@@ -71,7 +72,8 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
     dev = T.device
     n = T.shape[0]
     L = maxL - minL + 1
-    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels)
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
+                          rows_far, rows_refine, far_grid)
     nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
                             near_cols=near_cols, chunk_cols=chunk_cols)
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
@@ -99,7 +101,9 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
 
 
 def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, guard: float = 0.0,
-                   near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False):
+                   near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False,
+                   time_kernels: bool = False, rows_near: int = 0, rows_far: int = 0,
+                   rows_refine: int = 0, far_grid: int = 0):
     """All subsequences of length m whose nearest non-self match is >= r away.
 
     Returns (mask bool[N] on the device, nn_dist float64[N] valid where mask,
@@ -109,7 +113,8 @@ def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, gua
     dev = T.device
     n = T.shape[0]
     N = n - m + 1
-    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols)
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
+                          rows_far, rows_refine, far_grid)
     nbytes = workspace_size(n, m, m, 1, dist_bits=dist_bits, guard=guard, near_cols=near_cols,
                             chunk_cols=chunk_cols)
     ws = _workspace(nbytes, dev)

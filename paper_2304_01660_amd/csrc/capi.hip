@@ -57,16 +57,29 @@ struct Opts {
     int near_cols;
     int chunk_cols;
     unsigned int flags;
+    int rows_near, rows_far, rows_refine;
+    int far_grid;
 };
 
 int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 {
-    Opts r = {32, 1e-4f, 2048, 1024, 0u};
+    Opts r = {32, 1e-4f, 2048, 1024, 0u, 0, 0, 0, 2048};
     if (o) {
         if (o->flags & ~PALMAD_FLAG_TIME_KERNELS)
             return fail(ctx, PALMAD_EINVAL, "unknown option flags 0x%x", o->flags);
         r.flags = o->flags;
-        for (int i = 0; i < 7; ++i)
+        const int32_t rows[3] = {o->rows_near, o->rows_far, o->rows_refine};
+        for (int i = 0; i < 3; ++i)
+            if (rows[i] != 0 && rows[i] != 128 && rows[i] != 256 && rows[i] != 512)
+                return fail(ctx, PALMAD_EINVAL, "tile rows must be 0, 128, 256 or 512 (got %d)",
+                            rows[i]);
+        r.rows_near = o->rows_near;
+        r.rows_far = o->rows_far;
+        r.rows_refine = o->rows_refine;
+        if (o->far_grid < 0 || o->far_grid > 65536)
+            return fail(ctx, PALMAD_EINVAL, "far_grid must be in [0, 65536] (got %d)", o->far_grid);
+        if (o->far_grid > 0) r.far_grid = o->far_grid;
+        for (int i = 0; i < 3; ++i)
             if (o->reserved[i] != 0) return fail(ctx, PALMAD_EINVAL, "options.reserved must be zero");
         if (o->dist_bits != 0) {
             if (o->dist_bits != 32 && o->dist_bits != 64)
@@ -88,7 +101,7 @@ int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 
 // Largest length whose LDS staging (two centred windows + padding, FP64)
 // fits a 64 KiB workgroup allocation.
-constexpr int32_t MAXL_LIMIT = 4000;
+constexpr int32_t MAXL_LIMIT = 3000;
 
 int validate(palmad_ctx* ctx, int64_t n, int32_t minL, int32_t maxL, int32_t k)
 {
@@ -117,7 +130,13 @@ SweepCfg cfg_of(const Opts& o, const KernelTimer* timer)
     c.chunk_cols = o.chunk_cols;
     c.guard = o.dist_bits == 64 ? 0.0f : o.guard;
     c.dist_bits = o.dist_bits;
-    c.far_grid = 2048;
+    c.far_grid = o.far_grid;
+    const int near_rows = o.rows_near ? o.rows_near : (o.dist_bits == 64 ? 256 : 512);
+    const int far_rows = o.rows_far ? o.rows_far : near_rows;
+    const int ref_rows = o.rows_refine ? o.rows_refine : 128;
+    c.q_near = near_rows / 64;
+    c.q_far = far_rows / 64;
+    c.q_ref = ref_rows / 64;
     c.timer = timer;
     return c;
 }

@@ -11,9 +11,6 @@ namespace palmad {
 // Row-tile geometry of the sweeps: a tile is one wavefront of 64 lanes, each
 // lane owning Q consecutive rows (subsequence start indices).
 constexpr int WAVE = 64;
-constexpr int Q_SEL32 = 8;   // FP32 selection sweep: 512 rows per tile
-constexpr int Q_SEL64 = 4;   // FP64 selection sweep: 256 rows per tile
-constexpr int Q_REF = 2;     // FP64 refinement sweep: 128 rows per tile
 constexpr int R_MAX = 512;
 constexpr int KP_EXTRA = 4;  // candidates polished beyond k
 constexpr int K_MAX = 64;
@@ -112,6 +109,7 @@ struct SweepCfg {
     float guard;
     int dist_bits;
     int far_grid;     // workgroups of the split passes
+    int q_near, q_far, q_ref;  // rows per lane of each pass's tiles (2, 4 or 8)
     const KernelTimer* timer;
 };
 

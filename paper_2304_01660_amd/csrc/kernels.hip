@@ -88,6 +88,16 @@ __device__ __forceinline__ double dbl_of(unsigned long long u)
                      : __longlong_as_double((long long)~u);
 }
 
+// Values identical in every lane, made explicit so the compiler keeps them
+// (and everything derived from them) in scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v)
+{
+    const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)v);
+    const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) { return (int64_t)uniform64((unsigned long long)v); }
+
 __device__ __forceinline__ unsigned long long load_word(const unsigned long long* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -368,21 +378,49 @@ __device__ __forceinline__ void initial_column(const double* __restrict__ T,
     for (int q = 0; q < Q; ++q) acc[q] -= mu[rbase + q] * Sy;
 }
 
-// B(j0 + lane) = C(i0, j0 + lane): the exact top-boundary values of a block.
-__device__ __forceinline__ double boundary_dot(const double* __restrict__ T,
-                                               const double* __restrict__ mu, int32_t m,
-                                               int64_t j0, const double* xs, double Sx)
+// Column helpers of one step, staged in LDS per block of 64 columns.
+template <typename F>
+struct alignas(4 * sizeof(F)) H4 {
+    F df, dg, inv;  // df[j-1], dg[j-1], 1/(sqrt(m) sigma_j)
+    F B;            // C(i0, j): exact value of the tile's top row at column j
+};
+
+// LDS of a sweep work item, in doubles: xs[m+64] | win[m+128] | hs[256].
+// win holds the first column's centred window while the initial column is
+// computed, then the T segment of the current block.
+__host__ __device__ constexpr int sweep_hs_offset(int m) { return (2 * m + 192 + 3) & ~3; }
+__host__ __device__ constexpr size_t sweep_lds_doubles(int m) { return (size_t)(sweep_hs_offset(m) + 256); }
+
+// Stage the block starting at column j0 in LDS: one burst of independent
+// loads brings the T segment and the column helpers, then lane l computes
+// the exact top-boundary value B(j0 + l) = C(i0, j0 + l) from LDS.  hs[s]
+// then holds everything step s needs.
+template <typename F>
+__device__ __forceinline__ void stage_block(const double* __restrict__ T, const double* __restrict__ mu,
+                                            const F* __restrict__ df, const F* __restrict__ dg,
+                                            const F* __restrict__ inv, int32_t m, int64_t j0,
+                                            const double* xs, double Sx, double* win, H4<F>* hs)
 {
-    const int64_t jl = j0 + threadIdx.x;
-    const double* t = T + jl;
+    const int lane = threadIdx.x;
+    __syncthreads();  // the previous block is done with win and hs
+    const double muj = mu[j0 + lane];
+    H4<F> h;
+    h.df = df[j0 + lane - 1];
+    h.dg = dg[j0 + lane - 1];
+    h.inv = inv[j0 + lane];
+    for (int t = lane; t < m + 68; t += 64) win[t] = T[j0 + t];
+    __syncthreads();
+    const double* tw = win + lane;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int k = 0; k < m; k += 4) {
-        a0 = fma(xs[k], t[k], a0);
-        a1 = fma(xs[k + 1], t[k + 1], a1);
-        a2 = fma(xs[k + 2], t[k + 2], a2);
-        a3 = fma(xs[k + 3], t[k + 3], a3);
+        a0 = fma(xs[k], tw[k], a0);
+        a1 = fma(xs[k + 1], tw[k + 1], a1);
+        a2 = fma(xs[k + 2], tw[k + 2], a2);
+        a3 = fma(xs[k + 3], tw[k + 3], a3);
     }
-    return (a0 + a1) + (a2 + a3) - mu[jl] * Sx;
+    h.B = (F)((a0 + a1) + (a2 + a3) - muj * Sx);
+    hs[lane] = h;
+    __syncthreads();
 }
 
 // ----- sweep machinery shared by selection and refinement -----
@@ -407,7 +445,7 @@ __device__ __forceinline__ void rows_from_bitmap(const unsigned long long* alive
     const unsigned int msk = (Q >= 32) ? 0xffffffffu : ((1u << Q) - 1u);
     const unsigned int live = (unsigned int)(load_word(&alive[rbase >> 6]) >> (rbase & 63)) & msk;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) dm[q] = __ballot(!((live >> q) & 1u));
+    for (int q = 0; q < Q; ++q) dm[q] = uniform64(__ballot(!((live >> q) & 1u)));
 }
 
 // Publish rows dead locally but still set in the bitmap; absorb rows the
@@ -429,10 +467,10 @@ __device__ __forceinline__ bool sync_rows(unsigned long long* alive, int64_t rba
     unsigned long long all = ~0ull;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        dm[q] |= __ballot(!((live >> q) & 1u));
+        dm[q] = uniform64(dm[q] | __ballot(!((live >> q) & 1u)));
         all &= dm[q];
     }
-    return all != ~0ull;
+    return __builtin_amdgcn_readfirstlane((int)(all != ~0ull)) != 0;
 }
 
 __device__ __forceinline__ void kill_columns(unsigned long long* alive, int64_t j0,
@@ -451,7 +489,8 @@ __device__ __forceinline__ void kill_columns(unsigned long long* alive, int64_t 
 // Registers rotate: before step u of a group of Q steps, slot q lives in
 // C[(q - u) mod Q]; each register is updated in place, so the shift from
 // slot q-1 to slot q costs nothing and only slot 0 needs the DPP move from
-// the previous lane (lane 0 takes the exact boundary value Bv).
+// the previous lane.  Lane 0 keeps the DPP's old operand instead: Bv, the
+// exact boundary value of this step (identical in every lane).
 template <typename F, int Q, int U>
 __device__ __forceinline__ void advance(F (&C)[Q], const F (&a)[Q], const F (&b)[Q], F dfj, F dgj,
                                         F Bv)
@@ -471,55 +510,49 @@ __device__ __forceinline__ int slot_reg(int q)
 }
 
 // ----- selection sweep -----
-// One step U of a group: advance, then prune rows whose correlation with
-// column j exceeds the threshold and record whether column j was hit.
+// One step U of a group: advance, then the pruning margin of every slot,
+// C * inv_j - th = (rho - thr) / inv_i, which is > 0 exactly when the pair is
+// closer than r.  The row keeps its largest margin (folded into the dead
+// masks once per block); the column is hit when any slot's margin is > 0.
 // MASK: only pairs with j >= i + m count (the triangle next to the band).
 template <typename F, int Q, int U, bool MASK>
 __device__ __forceinline__ void sel_step(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
-                                         const F (&th)[Q], unsigned long long (&dm)[Q],
-                                         const int32_t (&ri)[Q], F dfj, F dgj, F invj, F& Bv,
-                                         int32_t jm, unsigned long long& colbits, int s)
+                                         const F (&nth)[Q], F (&rm)[Q], const int32_t (&ri)[Q],
+                                         F dfj, F dgj, F invj, F Bv, int32_t jm,
+                                         unsigned long long& colbits, int s)
 {
-    const F Bn = dpp_rol1(Bv);
     advance<F, Q, U>(C, a, b, dfj, dgj, Bv);
-    Bv = Bn;
-    unsigned long long any = 0ull;
+    F mg[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        bool h = C[slot_reg<Q, U>(q)] * invj > th[q];
-        if (MASK) h = h && (jm >= ri[q]);
-        const unsigned long long hb = __ballot(h);
-        dm[q] |= hb;
-        any |= hb;
+        mg[q] = f_fma(C[slot_reg<Q, U>(q)], invj, nth[q]);
+        if (MASK) mg[q] = (jm >= ri[q]) ? mg[q] : -f_inf<F>();
+        rm[q] = fmax(rm[q], mg[q]);
     }
-    if (any) colbits |= 1ull << s;
+    F cm = mg[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) cm = fmax(cm, mg[q]);
+    if (uniform64(__ballot(cm > F(0))) != 0ull) colbits |= 1ull << s;
 }
 
 template <typename F, int Q, bool MASK>
 __device__ __forceinline__ void sel_block(const SweepArgs<F>& A, int64_t j0, int nst, F (&C)[Q],
-                                          const F (&a)[Q], const F (&b)[Q], const F (&th)[Q],
-                                          unsigned long long (&dm)[Q], const int32_t (&ri)[Q], F Bv,
+                                          const F (&a)[Q], const F (&b)[Q], const F (&nth)[Q],
+                                          F (&rm)[Q], const int32_t (&ri)[Q], const H4<F>* hs,
                                           unsigned long long& colbits)
 {
-    const cptr<F> df = as_const(A.df);
-    const cptr<F> dg = as_const(A.dg);
-    const cptr<F> inv = as_const(A.inv);
     for (int s0 = 0; s0 < nst; s0 += Q) {
         const int64_t jg = j0 + s0;
-        F dfv[Q], dgv[Q], ivv[Q];
+        H4<F> hv[Q];
 #pragma unroll
-        for (int u = 0; u < Q; ++u) {
-            dfv[u] = df[jg + u - 1];
-            dgv[u] = dg[jg + u - 1];
-            ivv[u] = inv[jg + u];
-        }
+        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
         const int32_t jm = (int32_t)(jg - A.m);
         const int left = nst - s0;
-#define SEL_STEP(U)                                                                           \
-    if ((U) < left)                                                                           \
-        sel_step<F, Q, ((U) < Q ? (U) : 0), MASK>(C, a, b, th, dm, ri, dfv[(U) % Q],         \
-                                                  dgv[(U) % Q], ivv[(U) % Q], Bv, jm + (U), \
-                                                  colbits, s0 + (U));
+#define SEL_STEP(U)                                                                            \
+    if ((U) < left)                                                                            \
+        sel_step<F, Q, ((U) < Q ? (U) : 0), MASK>(C, a, b, nth, rm, ri, hv[(U) % Q].df,       \
+                                                  hv[(U) % Q].dg, hv[(U) % Q].inv,             \
+                                                  hv[(U) % Q].B, jm + (U), colbits, s0 + (U));
         static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
         SEL_STEP(0)
         SEL_STEP(1)
@@ -542,6 +575,9 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
                          double* lds, unsigned long long& evals)
 {
     constexpr int R = 64 * Q;
+    i0 = uniform_i64(i0);
+    jbeg = uniform_i64(jbeg);
+    jend = uniform_i64(jend);
     const int lane = threadIdx.x;
     const int32_t m = A.m;
     const int64_t N = A.N;
@@ -557,6 +593,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     }
     double* xs = lds;
     double* ys = lds + (m + 64);
+    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m));
     double Sx, Sy;
     stage_windows(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy);
     F C[Q];
@@ -566,7 +603,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
 #pragma unroll
         for (int q = 0; q < Q; ++q) C[q] = (F)acc[q];
     }
-    F a[Q], b[Q], th[Q];
+    F a[Q], b[Q], nth[Q], rm[Q];
     int32_t ri[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -576,35 +613,41 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         a[q] = top ? F(0) : A.df[ip];
         b[q] = top ? F(0) : A.dg[ip];
         const F invi = A.inv[i];
-        th[q] = (i < N && invi > F(0)) ? thr / invi : f_inf<F>();
+        // margin offset: C * inv_j - thr / inv_i > 0  <=>  rho > thr
+        nth[q] = (i < N && invi > F(0)) ? -(thr / invi) : -f_inf<F>();
         ri[q] = (int32_t)i;
+        rm[q] = -f_inf<F>();
     }
     // column jbeg
     {
         const F invj = A.inv[jbeg];
-        unsigned long long any = 0ull;
+        F cm = -f_inf<F>();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const bool h = (C[q] * invj > th[q]) && ((int32_t)(jbeg - m) >= ri[q]);
-            const unsigned long long hb = __ballot(h);
-            dm[q] |= hb;
-            any |= hb;
+            F mg = f_fma(C[q], invj, nth[q]);
+            mg = ((int32_t)(jbeg - m) >= ri[q]) ? mg : -f_inf<F>();
+            rm[q] = fmax(rm[q], mg);
+            cm = fmax(cm, mg);
         }
-        kill_columns(A.alive, jbeg, any ? 1ull : 0ull);
+        kill_columns(A.alive, jbeg, uniform64(__ballot(cm > F(0))) ? 1ull : 0ull);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(rm[q] > F(0)));
     }
     unsigned long long ev = pair_count(i0, std::min<int64_t>(i0 + R, N), jbeg, 1, m, false);
     bool go = sync_rows<Q>(A.alive, rbase, dm);
     int64_t j = jbeg + 1;
     while (go && j < jend) {
         const int nst = (int)std::min<int64_t>(64, jend - j);
-        const F Bv = (F)boundary_dot(A.T, A.mu, m, j, xs, Sx);
+        stage_block<F>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xs, Sx, ys, hs);
         unsigned long long colbits = 0ull;
         const bool full = (j - (i0 + R - 1)) >= m;
         if (full)
-            sel_block<F, Q, false>(A, j, nst, C, a, b, th, dm, ri, Bv, colbits);
+            sel_block<F, Q, false>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
         else
-            sel_block<F, Q, true>(A, j, nst, C, a, b, th, dm, ri, Bv, colbits);
+            sel_block<F, Q, true>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
         kill_columns(A.alive, j, colbits);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(rm[q] > F(0)));
         ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, false);
         j += nst;
         go = sync_rows<Q>(A.alive, rbase, dm);
@@ -619,8 +662,11 @@ __device__ __forceinline__ float sel_threshold<float>(const Ctrl* c) { return c-
 template <>
 __device__ __forceinline__ double sel_threshold<double>(const Ctrl* c) { return c->thr_sel; }
 
+// First selection pass: every row tile's nearest near_cols columns, split
+// into chunks of `chunk` columns that run concurrently (blockIdx.y); each
+// stops as soon as the whole tile is dead.
 template <typename F, int Q>
-__global__ __launch_bounds__(64) void k_select_near(SweepArgs<F> A, int near_cols)
+__global__ __launch_bounds__(64) void k_select_near(SweepArgs<F> A, int near_cols, int chunk)
 {
     extern __shared__ double lds[];
     const Ctrl* c = A.ctrl;
@@ -628,9 +674,10 @@ __global__ __launch_bounds__(64) void k_select_near(SweepArgs<F> A, int near_col
     constexpr int R = 64 * Q;
     const int64_t i0 = (int64_t)blockIdx.x * R;
     if (i0 >= A.N) return;
-    const int64_t jbeg = i0 + A.m;
-    if (jbeg >= A.N) return;
-    const int64_t jend = std::min<int64_t>(A.N, jbeg + near_cols);
+    const int64_t j00 = i0 + A.m;
+    const int64_t jbeg = j00 + (int64_t)blockIdx.y * chunk;
+    if (jbeg >= A.N || jbeg >= j00 + near_cols) return;
+    const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
     const F thr = sel_threshold<F>(c);
     unsigned long long ev = 0;
     sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
@@ -706,12 +753,10 @@ __global__ void k_tiles(const unsigned long long* __restrict__ alive, int64_t N,
 template <int Q, int U, int MASK>
 __device__ __forceinline__ void ref_step(double (&C)[Q], const double (&a)[Q], const double (&b)[Q],
                                          double (&mx)[Q], const int32_t (&ri)[Q], double dfj,
-                                         double dgj, double invj, double& Bv, int32_t jm,
+                                         double dgj, double invj, double Bv, int32_t jm,
                                          int32_t jp)
 {
-    const double Bn = dpp_rol1(Bv);
     advance<double, Q, U>(C, a, b, dfj, dgj, Bv);
-    Bv = Bn;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         double v = C[slot_reg<Q, U>(q)] * invj;
@@ -725,26 +770,20 @@ template <int Q, int MASK>
 __device__ __forceinline__ void ref_block(const SweepArgs<double>& A, int64_t j0, int nst,
                                           double (&C)[Q], const double (&a)[Q],
                                           const double (&b)[Q], double (&mx)[Q],
-                                          const int32_t (&ri)[Q], double Bv)
+                                          const int32_t (&ri)[Q], const H4<double>* hs)
 {
-    const cptr<double> df = as_const(A.df);
-    const cptr<double> dg = as_const(A.dg);
-    const cptr<double> inv = as_const(A.inv);
     for (int s0 = 0; s0 < nst; s0 += Q) {
         const int64_t jg = j0 + s0;
-        double dfv[Q], dgv[Q], ivv[Q];
+        H4<double> hv[Q];
 #pragma unroll
-        for (int u = 0; u < Q; ++u) {
-            dfv[u] = df[jg + u - 1];
-            dgv[u] = dg[jg + u - 1];
-            ivv[u] = inv[jg + u];
-        }
+        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
         const int32_t jm = (int32_t)(jg - A.m), jp = (int32_t)(jg + A.m);
         const int left = nst - s0;
-#define REF_STEP(U)                                                                         \
-    if ((U) < left)                                                                         \
-        ref_step<Q, ((U) < Q ? (U) : 0), MASK>(C, a, b, mx, ri, dfv[(U) % Q], dgv[(U) % Q], \
-                                               ivv[(U) % Q], Bv, jm + (U), jp + (U));
+#define REF_STEP(U)                                                                             \
+    if ((U) < left)                                                                             \
+        ref_step<Q, ((U) < Q ? (U) : 0), MASK>(C, a, b, mx, ri, hv[(U) % Q].df, hv[(U) % Q].dg, \
+                                               hv[(U) % Q].inv, hv[(U) % Q].B, jm + (U),        \
+                                               jp + (U));
         static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
         REF_STEP(0)
         REF_STEP(1)
@@ -767,6 +806,9 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
                          bool left, double thr, int prune, double* lds, unsigned long long& evals)
 {
     constexpr int R = 64 * Q;
+    i0 = uniform_i64(i0);
+    jbeg = uniform_i64(jbeg);
+    jend = uniform_i64(jend);
     const int lane = threadIdx.x;
     const int32_t m = A.m;
     const int64_t N = A.N;
@@ -783,6 +825,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     }
     double* xs = lds;
     double* ys = lds + (m + 64);
+    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m));
     double Sx, Sy;
     stage_windows(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy);
     double C[Q];
@@ -813,18 +856,18 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     bool go = true;
     while (go && j < jend) {
         const int nst = (int)std::min<int64_t>(64, jend - j);
-        const double Bv = boundary_dot(A.T, A.mu, m, j, xs, Sx);
+        stage_block<double>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xs, Sx, ys, hs);
         bool full;
         if (left) full = (i0 - (j + nst - 1)) >= m;
         else full = (j - (i0 + R - 1)) >= m;
-        if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, Bv);
-        else if (left) ref_block<Q, 2>(A, j, nst, C, a, b, mx, ri, Bv);
-        else ref_block<Q, 1>(A, j, nst, C, a, b, mx, ri, Bv);
+        if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, hs);
+        else if (left) ref_block<Q, 2>(A, j, nst, C, a, b, mx, ri, hs);
+        else ref_block<Q, 1>(A, j, nst, C, a, b, mx, ri, hs);
         ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, left);
         j += nst;
         if (prune) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) dm[q] |= __ballot(invi[q] > 0.0 && mx[q] * invi[q] > thr);
+            for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(invi[q] > 0.0 && mx[q] * invi[q] > thr));
         }
         go = sync_rows<Q>(A.alive, rbase, dm);
     }
@@ -839,7 +882,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
             const bool partner = (flo >= 0 && flo <= i - m) || (fhi >= 0 && fhi >= i + m);
             mx[q] = partner ? 1.0 : 0.0;
         }
-        if (prune) dm[q] |= __ballot(flat[q] && mx[q] > thr);
+        if (prune) dm[q] |= uniform64(__ballot(flat[q] && mx[q] > thr));
     }
     sync_rows<Q>(A.alive, rbase, dm);
 #pragma unroll
@@ -956,23 +999,67 @@ SweepArgs<double> sweep_args<double>(const Layout& lay, const Buffers& b, int32_
 }
 
 template <typename F, int Q>
-static void launch_select(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                          hipStream_t st)
+static void launch_near(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
+                        hipStream_t st)
 {
     constexpr int R = 64 * Q;
     const SweepArgs<F> A = sweep_args<F>(lay, b, m);
-    const int64_t N = A.N;
-    const size_t lds = sizeof(double) * (size_t)(2 * (m + 64));
-    const int ntiles = (int)((N + R - 1) / R);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
+    const int ntiles = (int)((A.N + R - 1) / R);
+    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
     cfg.timer->begin(0, st);
-    hipLaunchKernelGGL((k_select_near<F, Q>), dim3(ntiles), dim3(64), lds, st, A, cfg.near_cols);
+    hipLaunchKernelGGL((k_select_near<F, Q>), dim3(ntiles, nsub), dim3(64), lds, st, A,
+                       cfg.near_cols, cfg.chunk_cols);
     cfg.timer->end(0, st);
-    hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, N, m, R, 0,
+}
+
+template <typename F, int Q>
+static void launch_far(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
+                       hipStream_t st)
+{
+    constexpr int R = 64 * Q;
+    const SweepArgs<F> A = sweep_args<F>(lay, b, m);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
+    const int ntiles = (int)((A.N + R - 1) / R);
+    hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, A.N, m, R, 0,
                        cfg.near_cols, cfg.chunk_cols, b.tsel, b.ctrl);
     cfg.timer->begin(1, st);
     hipLaunchKernelGGL((k_select_far<F, Q>), dim3(cfg.far_grid), dim3(64), lds, st, A, b.tsel,
                        cfg.near_cols, cfg.chunk_cols);
     cfg.timer->end(1, st);
+}
+
+template <int Q>
+static void launch_refine(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
+                          hipStream_t st)
+{
+    constexpr int R = 64 * Q;
+    const SweepArgs<double> A = sweep_args<double>(lay, b, m);
+    const int ntiles = (int)((A.N + R - 1) / R);
+    hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, A.N, m, R, 1,
+                       0, cfg.chunk_cols, b.tref, b.ctrl);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
+    cfg.timer->begin(2, st);
+    hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, A, b.tref,
+                       cfg.chunk_cols);
+    cfg.timer->end(2, st);
+}
+
+// Row tiles of 128, 256 or 512 subsequences (Q = 2, 4, 8 rows per lane).
+template <typename F>
+static void launch_select(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
+                          hipStream_t st)
+{
+    switch (cfg.q_near) {
+    case 2: launch_near<F, 2>(lay, b, cfg, m, st); break;
+    case 4: launch_near<F, 4>(lay, b, cfg, m, st); break;
+    default: launch_near<F, 8>(lay, b, cfg, m, st); break;
+    }
+    switch (cfg.q_far) {
+    case 2: launch_far<F, 2>(lay, b, cfg, m, st); break;
+    case 4: launch_far<F, 4>(lay, b, cfg, m, st); break;
+    default: launch_far<F, 8>(lay, b, cfg, m, st); break;
+    }
 }
 
 hipError_t launch_round(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
@@ -987,20 +1074,13 @@ hipError_t launch_round(const Layout& lay, const Buffers& b, const SweepCfg& cfg
                            lay.nwords);
     }
     if (cfg.dist_bits == 64)
-        launch_select<double, Q_SEL64>(lay, b, cfg, m, st);
+        launch_select<double>(lay, b, cfg, m, st);
     else
-        launch_select<float, Q_SEL32>(lay, b, cfg, m, st);
-    {
-        constexpr int R = 64 * Q_REF;
-        const int ntiles = (int)((N + R - 1) / R);
-        hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, N, m, R,
-                           1, 0, cfg.chunk_cols, b.tref, b.ctrl);
-        const SweepArgs<double> A = sweep_args<double>(lay, b, m);
-        const size_t lds = sizeof(double) * (size_t)(2 * (m + 64));
-        cfg.timer->begin(2, st);
-        hipLaunchKernelGGL((k_refine<Q_REF>), dim3(cfg.far_grid), dim3(64), lds, st, A, b.tref,
-                           cfg.chunk_cols);
-        cfg.timer->end(2, st);
+        launch_select<float>(lay, b, cfg, m, st);
+    switch (cfg.q_ref) {
+    case 4: launch_refine<4>(lay, b, cfg, m, st); break;
+    case 8: launch_refine<8>(lay, b, cfg, m, st); break;
+    default: launch_refine<2>(lay, b, cfg, m, st); break;
     }
     {
         const int64_t nw = (N + 63) / 64;
@@ -1076,93 +1156,102 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_topk(const int32_t* __restrict__
     if (threadIdx.x == 0) c->ncand = (unsigned int)kp;
 }
 
-// Exact FP64 nearest-neighbour correlation of candidate rows against every
-// column (direct centred dot products, no recurrence).  Partial (max, argmax)
-// per block of 256 columns.
+// Exact FP64 nearest-neighbour correlation of the candidate rows against
+// every column: direct centred dot products (no recurrence), the reference
+// the reported distances and neighbour indices come from.  A block owns 256
+// consecutive columns, stages their windows in LDS once and evaluates every
+// candidate against them; it writes one (max rho, argmax j) partial per
+// candidate.
 __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restrict__ T,
                                                          const double* __restrict__ mu,
                                                          const double* __restrict__ var, int64_t N,
                                                          int32_t m, const int64_t* __restrict__ cand,
                                                          Ctrl* c, double* part, int64_t npart)
 {
-    extern __shared__ double xs[];
+    extern __shared__ double lds[];
+    double* ts = lds;                        // T[j0 .. j0 + 256 + m + 64)
+    double* xs = lds + POLISH_BLOCK + m + 64; // centred candidate window, zero padded
     __shared__ double sh[16];
     __shared__ double red_v[POLISH_BLOCK / 64];
     __shared__ long long red_j[POLISH_BLOCK / 64];
-    const int cid = blockIdx.y;
-    if ((unsigned int)cid >= c->ncand) return;
-    const int64_t i = cand[cid];
-    const double mui = mu[i];
-    double sx = 0.0;
-    for (int k = threadIdx.x; k < m + 64; k += POLISH_BLOCK) {
-        const double x = k < m ? T[i + k] - mui : 0.0;
-        xs[k] = x;
-        sx += x;
-    }
-    const double s0 = block_sum(sx, sh);
-    if (threadIdx.x == 0) sh[15] = s0;
-    __syncthreads();
-    const double Sx = sh[15];
+    const int ncand = (int)c->ncand;
+    if (ncand == 0) return;
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * POLISH_BLOCK;
+    for (int t = tid; t < POLISH_BLOCK + m + 64; t += POLISH_BLOCK) ts[t] = T[j0 + t];
+    const int64_t j = j0 + tid;
     const double feps = c->flat_eps;
-    const double sgi = sqrt(var[i]);
-    const bool flat_i = sgi <= feps;
-    double best = -f_inf<double>();
-    long long bj = 0x7fffffffffffffffll;
+    const bool colok = j < N;
+    const double sgj = colok ? sqrt(var[j]) : 1.0;
+    const double muj = colok ? mu[j] : 0.0;
+    const bool flat_j = colok && sgj <= feps;
     unsigned long long ev = 0;
-    for (int64_t j = (int64_t)blockIdx.x * POLISH_BLOCK + threadIdx.x; j < N;
-         j += (int64_t)gridDim.x * POLISH_BLOCK) {
-        if (j > i - m && j < i + m) continue;
-        const double sgj = sqrt(var[j]);
-        const bool flat_j = sgj <= feps;
-        double rho;
-        if (flat_i || flat_j) {
-            rho = (flat_i && flat_j) ? 1.0 : 0.0;
-        } else {
-            const double* t = T + j;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            for (int k = 0; k < m; k += 4) {
-                a0 = fma(xs[k], t[k], a0);
-                a1 = fma(xs[k + 1], t[k + 1], a1);
-                a2 = fma(xs[k + 2], t[k + 2], a2);
-                a3 = fma(xs[k + 3], t[k + 3], a3);
-            }
-            const double C = (a0 + a1) + (a2 + a3) - mu[j] * Sx;
-            rho = C / ((double)m * sgi * sgj);
-            rho = fmin(1.0, fmax(-1.0, rho));
+    for (int cid = 0; cid < ncand; ++cid) {
+        const int64_t i = cand[cid];
+        const double mui = mu[i];
+        double sx = 0.0;
+        __syncthreads();  // previous candidate's xs fully consumed
+        for (int k = tid; k < m + 64; k += POLISH_BLOCK) {
+            const double x = k < m ? T[i + k] - mui : 0.0;
+            xs[k] = x;
+            sx += x;
         }
-        ++ev;
-        if (rho > best) {
+        const double s0 = block_sum(sx, sh);
+        if (tid == 0) sh[15] = s0;
+        __syncthreads();
+        const double Sx = sh[15];
+        const double sgi = sqrt(var[i]);
+        const bool flat_i = sgi <= feps;
+        double best = -f_inf<double>();
+        long long bj = 0x7fffffffffffffffll;
+        if (colok && (j <= i - m || j >= i + m)) {
+            double rho;
+            if (flat_i || flat_j) {
+                rho = (flat_i && flat_j) ? 1.0 : 0.0;
+            } else {
+                const double* t = ts + tid;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                for (int k = 0; k < m; k += 4) {
+                    a0 = fma(xs[k], t[k], a0);
+                    a1 = fma(xs[k + 1], t[k + 1], a1);
+                    a2 = fma(xs[k + 2], t[k + 2], a2);
+                    a3 = fma(xs[k + 3], t[k + 3], a3);
+                }
+                const double C = (a0 + a1) + (a2 + a3) - muj * Sx;
+                rho = C / ((double)m * sgi * sgj);
+                rho = fmin(1.0, fmax(-1.0, rho));
+            }
             best = rho;
             bj = j;
+            ++ev;
         }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        const double v = __shfl_xor(best, o);
-        const long long jj = __shfl_xor(bj, o);
-        if (v > best || (v == best && jj < bj)) {
-            best = v;
-            bj = jj;
-        }
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red_v[w] = best;
-        red_j[w] = bj;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < POLISH_BLOCK / 64; ++q) {
-            if (red_v[q] > best || (red_v[q] == best && red_j[q] < bj)) {
-                best = red_v[q];
-                bj = red_j[q];
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double v = __shfl_xor(best, o);
+            const long long jj = __shfl_xor(bj, o);
+            if (v > best || (v == best && jj < bj)) {
+                best = v;
+                bj = jj;
             }
         }
-        const int64_t slot = ((int64_t)cid * npart + blockIdx.x) * 2;
-        part[slot] = best;
-        part[slot + 1] = (double)bj;
+        const int w = tid >> 6;
+        if ((tid & 63) == 0) {
+            red_v[w] = best;
+            red_j[w] = bj;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < POLISH_BLOCK / 64; ++q)
+                if (red_v[q] > best || (red_v[q] == best && red_j[q] < bj)) {
+                    best = red_v[q];
+                    bj = red_j[q];
+                }
+            const int64_t slot = ((int64_t)cid * npart + blockIdx.x) * 2;
+            part[slot] = best;
+            part[slot + 1] = (double)bj;
+        }
     }
     ev = (unsigned long long)wave_sum((double)ev);
-    if ((threadIdx.x & 63) == 0 && ev) atomicAdd(&c->evals_pol, ev);
+    if ((tid & 63) == 0 && ev) atomicAdd(&c->evals_pol, ev);
 }
 
 // Reduce the polish partials of each candidate to (rho, j) in part's tail.
@@ -1265,10 +1354,10 @@ hipError_t launch_finish_length(const Layout& lay, const Buffers& b, const Sweep
     const int64_t N = lay.n - m + 1;
     hipLaunchKernelGGL(k_topk, dim3(1), dim3(TOPK_BLOCK), 0, st, b.surv, b.rho, b.ctrl, lay.k,
                        b.cand);
-    const size_t lds = sizeof(double) * (size_t)(m + 64);
+    const size_t lds = sizeof(double) * (size_t)(POLISH_BLOCK + 2 * (m + 64));
     cfg.timer->begin(3, st);
-    hipLaunchKernelGGL(k_polish, dim3((unsigned int)lay.npart, lay.kp), dim3(POLISH_BLOCK), lds, st,
-                       b.T, b.mu, b.var, N, m, b.cand, b.ctrl, b.part, lay.npart);
+    hipLaunchKernelGGL(k_polish, dim3((unsigned int)lay.npart), dim3(POLISH_BLOCK), lds, st, b.T,
+                       b.mu, b.var, N, m, b.cand, b.ctrl, b.part, lay.npart);
     cfg.timer->end(3, st);
     hipLaunchKernelGGL(k_polish_reduce, dim3(lay.kp), dim3(256), 0, st, b.part, lay.npart, b.ctrl);
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(KP_MAX < 64 ? 64 : 128), 0, st, b.cand, b.part,

@@ -46,7 +46,7 @@ def _ws(n, minL, maxL, k, **kw):
     (100, 10, 34, 1, -1),        # n < 3*maxL - 1
     (1000, 10, 20, 0, -1),       # k < 1
     (1000, 10, 20, 65, -6),      # k above the supported maximum
-    (10**6, 10, 5000, 1, -6),    # maxL above the supported maximum
+    (10**6, 10, 3001, 1, -6),    # maxL above the supported maximum
 ])
 def test_workspace_size_rejects_bad_arguments(n, minL, maxL, k, code):
     rc, _ = _ws(n, minL, maxL, k)
@@ -66,8 +66,12 @@ def test_options_validation():
     assert rc == -1
     rc, _ = _ws(1000, 10, 20, 1, dist_bits=64)
     assert rc == 0
+    rc, _ = _ws(1000, 10, 20, 1, rows_near=300)
+    assert rc == -1
+    rc, _ = _ws(1000, 10, 20, 1, rows_near=128, rows_far=256, rows_refine=512)
+    assert rc == 0
     o = _lib.make_options()
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     b = ctypes.c_size_t(0)
     assert _lib.lib().palmad_workspace_size(1000, 10, 20, 1, ctypes.byref(o), ctypes.byref(b)) == -1
 

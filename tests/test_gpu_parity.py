@@ -145,6 +145,23 @@ def test_discords_match_bruteforce_tiny(dist_bits):
         _check_against_profiles(T, out, minL, maxL, k)
 
 
+@pytest.mark.parametrize("rows", [(128, 128, 128), (256, 512, 256), (512, 128, 512),
+                                  (128, 256, 256)])
+@pytest.mark.parametrize("dist_bits", [64, 32])
+def test_tile_heights_match_bruteforce(dist_bits, rows):
+    """Every row-tile height of every pass (separate kernel instantiations)."""
+    dev = _dev()
+    api = _api()
+    rn, rf, rr = rows
+    for c, kind, n, minL, maxL, k in list(_tiny_cases())[:6]:
+        T = synth.small_random(7000 + c, n, kind)
+        _say("tiles", dist_bits, rows, c, kind, n, minL, maxL, k)
+        out = api.discords(torch.from_numpy(T).to(dev), minL, maxL, k, dist_bits=dist_bits,
+                           rows_near=rn, rows_far=rf, rows_refine=rr, near_cols=256,
+                           chunk_cols=128)
+        _check_against_profiles(T, out, minL, maxL, k)
+
+
 def test_config1_matches_golden():
     dev = _dev()
     api = _api()
