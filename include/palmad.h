@@ -171,6 +171,36 @@ int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m
                           void* stream);
 
 /*
+ * Bytes of device workspace palmad_discords_backward() needs for K reported
+ * rows of lengths <= maxm in a series of length n.  Pure host computation;
+ * PALMAD_EINVAL unless 3 <= maxm, n >= 3*maxm - 1 and K >= 0.
+ */
+int palmad_backward_workspace_size(int64_t n, int64_t K, int32_t maxm, size_t* bytes);
+
+/*
+ * Gradient of reported nearest-neighbour distances with respect to the
+ * series (not in the paper: the adjoint of Eq. (4)-(6) at a fixed nearest
+ * neighbour).  For every q < K, with i = idx[q], m = len[q]:
+ *   grad_T += grad_nn[q] * d nnDist_m(i) / dT,
+ * where nnDist_m(i) = min over non-self matches j of the z-normalised
+ * distance.  The minimiser j* is recomputed on the device (direct FP64
+ * dot products, smallest j on ties) and the derivative is taken with j*
+ * held fixed (it is piecewise constant); a zero distance or a flat window
+ * contributes nothing.  Rows with an invalid (i, m) contribute nothing and
+ * report nn_idx = -1.
+ *
+ *   T        device, float64[n];  idx device int64[K];  len device int32[K]
+ *   grad_nn  device, float64[K]
+ *   grad_T   device, float64[n], accumulated (+=); the caller zeroes it.
+ *   nn_idx   device, int64[K] (optional, NULL): the recomputed j*.
+ * Scatter uses FP64 atomics, so summation order (last bits) can vary.
+ */
+int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_t K, int32_t maxm,
+                             const int64_t* idx, const int32_t* len, const double* grad_nn,
+                             void* workspace, size_t ws_bytes, double* grad_T, int64_t* nn_idx,
+                             void* stream);
+
+/*
  * Mean and population standard deviation of every window of length m, as
  * the search computes them: direct two-pass sums at length minL (Eq. (4)),
  * then the recurrences of Eq. (7)-(8) for minL+1 .. m.

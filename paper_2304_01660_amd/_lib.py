@@ -92,6 +92,10 @@ SIGNATURES = {
                                              _vp]),
     "palmad_window_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                            _vp, _vp]),
+    "palmad_backward_workspace_size": (ctypes.c_int, [_i64, _i64, _i32,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "palmad_discords_backward": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, _vp,
+                                                ctypes.c_size_t, _vp, _vp, _vp]),
 }
 
 _lib = None

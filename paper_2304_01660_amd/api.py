@@ -153,3 +153,67 @@ def window_stats(T: torch.Tensor, minL: int, m: int):
                                         ctypes.c_void_p(sg.data_ptr()), _stream(dev))
     _lib.check(rc, ctx)
     return mu, sg
+
+
+def discords_backward(T: torch.Tensor, idx: torch.Tensor, length: torch.Tensor,
+                      grad_nn: torch.Tensor, maxm: int | None = None, grad_T=None,
+                      return_nn_idx: bool = False):
+    """grad_T += sum_q grad_nn[q] * d nnDist(idx[q], len[q]) / dT (FP64).
+
+    The nearest neighbour of every row is recomputed on the device; see
+    palmad_discords_backward in include/palmad.h.
+    """
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    idx = idx.to(device=dev, dtype=torch.int64).contiguous()
+    length = length.to(device=dev, dtype=torch.int32).contiguous()
+    g = grad_nn.to(device=dev, dtype=torch.float64).contiguous()
+    K = idx.numel()
+    if maxm is None:
+        maxm = int(length.max().item()) if K else 3
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_backward_workspace_size(n, K, int(maxm), ctypes.byref(nbytes)))
+    ws = _workspace(int(nbytes.value), dev)
+    if grad_T is None:
+        grad_T = torch.zeros(n, dtype=torch.float64, device=dev)
+    nnj = torch.empty(max(K, 1), dtype=torch.int64, device=dev)
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_discords_backward(
+        ctx, ctypes.c_void_p(T.data_ptr()), n, K, int(maxm), ctypes.c_void_p(idx.data_ptr()),
+        ctypes.c_void_p(length.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(grad_T.data_ptr()),
+        ctypes.c_void_p(nnj.data_ptr()), _stream(dev))
+    _lib.check(rc, ctx)
+    if return_nn_idx:
+        return grad_T, nnj[:K]
+    return grad_T
+
+
+class DiscordNNDist(torch.autograd.Function):
+    """nnDist of the top-k discords of every length, differentiable in T.
+
+    forward(T, minL, maxL, k, options dict) -> (nn_dist, idx, len, nn_idx);
+    only nn_dist carries a gradient.  The backward pass recomputes each
+    reported row's nearest neighbour on the device and scatters the
+    closed-form derivative (held at that neighbour) into dL/dT.
+    """
+
+    @staticmethod
+    def forward(ctx, T, minL, maxL, k, options=None):
+        out = discords(T.detach(), int(minL), int(maxL), int(k), **(options or {}))
+        ctx.save_for_backward(T.detach(), out["idx"], out["len"])
+        ctx.maxL = int(maxL)
+        ctx.mark_non_differentiable(out["idx"], out["len"], out["nn_idx"])
+        return out["nn_dist"], out["idx"], out["len"], out["nn_idx"]
+
+    @staticmethod
+    def backward(ctx, g_nn, g_idx=None, g_len=None, g_nnidx=None):
+        T, idx, ln = ctx.saved_tensors
+        gT = discords_backward(T, idx, ln, g_nn, maxm=ctx.maxL)
+        return gT.to(T.dtype), None, None, None, None
+
+
+def discord_nn_dist(T: torch.Tensor, minL: int, maxL: int, k: int, **options):
+    """Differentiable nnDist[L*k] of the top-k discords (see DiscordNNDist)."""
+    return DiscordNNDist.apply(T, minL, maxL, k, options)[0]

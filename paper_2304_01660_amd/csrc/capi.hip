@@ -7,6 +7,7 @@
 // search to learn whether the length produced k discords.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -365,6 +366,74 @@ int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return read_stats(ctx, b, stats, secs, timer, st);
+}
+
+namespace {
+struct BwdLayout {
+    Layout lay;
+    int64_t nblk;
+    size_t off_part, total;
+};
+bool bwd_layout(int64_t n, int64_t K, int32_t maxm, BwdLayout* out)
+{
+    BwdLayout b = {};
+    make_layout(n, maxm, maxm, 1, 64, &b.lay);
+    b.lay.L = 0;  // no length history
+    b.nblk = (n + 255) / 256;
+    b.off_part = b.lay.total;
+    b.total = b.off_part + (((size_t)std::max<int64_t>(K, 1) * (size_t)b.nblk * 2 * sizeof(double) +
+                             255) & ~(size_t)255);
+    *out = b;
+    return true;
+}
+}  // namespace
+
+int palmad_backward_workspace_size(int64_t n, int64_t K, int32_t maxm, size_t* bytes)
+{
+    palmad_ctx* ctx = nullptr;
+    if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
+    if (K < 0) return fail(nullptr, PALMAD_EINVAL, "K must be >= 0");
+    int rc = validate(nullptr, n, maxm, maxm, 1);
+    if (rc) return rc;
+    BwdLayout b;
+    bwd_layout(n, K, maxm, &b);
+    *bytes = b.total;
+    (void)ctx;
+    return PALMAD_OK;
+}
+
+int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_t K, int32_t maxm,
+                             const int64_t* idx, const int32_t* len, const double* grad_nn,
+                             void* workspace, size_t ws_bytes, double* grad_T, int64_t* nn_idx,
+                             void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (K < 0) return fail(ctx, PALMAD_EINVAL, "K must be >= 0");
+    if (!T || !grad_T || (K > 0 && (!idx || !len || !grad_nn)))
+        return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    int rc = validate(ctx, n, maxm, maxm, 1);
+    if (rc) return rc;
+    if (K > 65535) return fail(ctx, PALMAD_EUNSUPPORTED, "K (%lld) above 65535", (long long)K);
+    BwdLayout bl;
+    bwd_layout(n, K, maxm, &bl);
+    if (!workspace) return fail(ctx, PALMAD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255u) != 0)
+        return fail(ctx, PALMAD_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < bl.total)
+        return fail(ctx, PALMAD_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    bl.total);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const Buffers b = carve(workspace, bl.lay);
+    rc = prepare(ctx, bl.lay, b, T, st);
+    if (rc) return rc;
+    if (K == 0) return PALMAD_OK;
+    HIP_TRY(launch_set_max_len(b, maxm, st));
+    double* part = (double*)((char*)workspace + bl.off_part);
+    HIP_TRY(launch_adjoint(b.T, n, K, maxm, idx, len, grad_nn, b.ctrl, part, bl.nblk, grad_T,
+                           nn_idx, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PALMAD_OK;
 }
 
 int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,

@@ -124,6 +124,11 @@ hipError_t launch_finish_length(const Layout& lay, const Buffers& b, const Sweep
 hipError_t launch_set_fixed_r(const Buffers& b, double r, hipStream_t st);
 hipError_t launch_range_out(const Layout& lay, const Buffers& b, int32_t m,
                             unsigned long long* alive_out, double* nn_out, hipStream_t st);
+hipError_t launch_adjoint(const double* Tpad, int64_t n, int64_t K, int32_t maxm,
+                          const int64_t* idx, const int32_t* len, const double* gin,
+                          const Ctrl* ctrl, double* part, int64_t nblk, double* grad,
+                          int64_t* jstar, hipStream_t st);
+hipError_t launch_set_max_len(const Buffers& b, int32_t maxm, hipStream_t st);
 hipError_t launch_stats_out(const Layout& lay, const Buffers& b, int32_t m, double* mu,
                             double* sigma, hipStream_t st);
 

@@ -1372,6 +1372,14 @@ __global__ void k_set_fixed_r(Ctrl* c, double r)
     c->r = r;
 }
 
+__global__ void k_set_max_len(Ctrl* c, int32_t maxm) { c->m = maxm; }
+
+hipError_t launch_set_max_len(const Buffers& b, int32_t maxm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_max_len, dim3(1), dim3(1), 0, st, b.ctrl, maxm);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_fixed_r(const Buffers& b, double r, hipStream_t st)
 {
     hipLaunchKernelGGL(k_set_fixed_r, dim3(1), dim3(1), 0, st, b.ctrl, r);
