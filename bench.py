@@ -65,6 +65,63 @@ def cpu_baseline(w, golden, n_lengths: int):
     }
 
 
+def batched_vs_plain(api, synth, torch, dev, reps: int):
+    """64 uneven series (lengths log-uniform in [1e4, 2e5], each with its own
+    length range of 51 lengths, top-1): one batched call against a loop of
+    single-series calls over the same series (best of graph replay and direct
+    launches for the loop)."""
+    ws = synth.config4()
+    vals = [torch.from_numpy(w.T).to(dev) for w in ws]
+    lo = [w.minL for w in ws]
+    hi = [w.maxL for w in ws]
+    lengths = sum(h - l + 1 for l, h in zip(lo, hi))
+    nb = api.batched_workspace_size([v.shape[0] for v in vals], lo, hi, 1)
+    wsb = torch.empty(nb, dtype=torch.uint8, device=dev)
+    flat = torch.cat(vals)
+    sizes = [v.shape[0] for v in vals]
+    res = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res, st = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb,
+                                       return_stats=True)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    evals_b = st["evals_select"] + st["evals_refine"] + st["evals_polish"]
+    wss = [torch.empty(api.workspace_size(w.n, w.minL, w.maxL, 1), dtype=torch.uint8, device=dev)
+           for w in ws]
+    plain = {}
+    for graphs in (True, False):
+        for b, w in enumerate(ws):  # warm-up
+            api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], graphs=graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            outs = [api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], graphs=graphs)
+                    for b, w in enumerate(ws)]
+        torch.cuda.synchronize()
+        plain[graphs] = (time.perf_counter() - t0) / reps
+    same = all(torch.equal(res[b][key], outs[b][key]) for b in range(len(ws))
+               for key in ("idx", "nn_dist", "nn_idx", "count"))
+    t_plain = min(plain.values())
+    return {
+        "workload": "batch64_rw+ecg_n1e4-2e5_m(50..100)+50_k1_fp32",
+        "series": len(ws),
+        "points": int(sum(sizes)),
+        "lengths": lengths,
+        "batched_s": t_batched,
+        "batched_lengths_per_s": lengths / t_batched,
+        "batched_evals_per_s": evals_b / t_batched,
+        "plain_loop_s": t_plain,
+        "plain_loop_lengths_per_s": lengths / t_plain,
+        "plain_loop_graph_s": plain[True],
+        "plain_loop_direct_s": plain[False],
+        "speedup": t_plain / t_batched,
+        "results_identical": bool(same),
+        "reps": reps,
+    }
+
+
 def check_golden(out, golden, T):
     import numpy as np
     if golden is None:
@@ -87,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-lengths", type=int, default=6)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding "
@@ -108,12 +167,25 @@ def main():
         api.discords(T, w.minL, w.maxL, w.k, workspace=ws)
     torch.cuda.synchronize()
 
-    agg = None
+    # timed region: the production path (round graphs replayed, no events)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True,
-                           time_kernels=True)
-        st = out["stats"]
+        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    st_prod = out["stats"]
+
+    # the same steps again with HIP events around every sweep launch, on the
+    # library's stream where the kernels run: per-kernel device time
+    agg = None
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        out_t = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True,
+                             time_kernels=True)
+        st = out_t["stats"]
         if agg is None:
             agg = {k: (list(v) if isinstance(v, list) else v) for k, v in st.items()}
         else:
@@ -123,11 +195,13 @@ def main():
                 else:
                     agg[k] += v
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
+    ms_instrumented = (time.perf_counter() - t1) / args.steps * 1e3
+    for key in ("idx", "nn_dist", "nn_idx", "count"):
+        if not torch.equal(out[key], out_t[key]):
+            raise SystemExit("instrumented and production runs disagree")
     parity = check_golden(out, golden, w.T)
 
-    evals = agg["evals_select"] + agg["evals_refine"] + agg["evals_polish"]
+    evals = (st_prod["evals_select"] + st_prod["evals_refine"] + st_prod["evals_polish"]) * args.steps
     kernels = {}
     for ci, name in enumerate(("select_near", "select_far", "refine", "polish")):
         launches = agg["kernel_launches"][ci]
@@ -157,6 +231,7 @@ def main():
         "evals_per_launch": (dk["evals_per_step"] / dk["launches_per_step"]
                              if dk["launches_per_step"] else None),
     }
+    batched = None if args.no_batched else batched_vs_plain(api, synth, torch, dev, args.batch_reps)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_lengths)
@@ -180,10 +255,12 @@ def main():
             "series": "seeded random walk with 5 injected sine bursts/level shifts (seed 1)",
         },
         "evals_per_s": evals / dt,
-        "range_searches_per_step": agg["range_searches"] / args.steps,
+        "range_searches_per_step": st_prod["range_searches"],
+        "ms_per_step_instrumented": ms_instrumented,
         "kernels": kernels,
         "parity_vs_oracle": parity,
         "roofline": roofline,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -21,14 +21,18 @@
  *     equal nnDist values are ordered by smaller index; a nearest-neighbour
  *     tie reports the smaller neighbour index.
  *   - Pointers documented as "device" must point to memory of the context's
- *     device; the library never frees or retains them.  Calls are issued on
- *     the HIP stream given to the call and return after the result is
- *     complete (the adaptive r loop reads one flag per range search).
+ *     device; the library never frees or retains them.  A call runs on the
+ *     context's own stream, after the work already queued on the HIP stream
+ *     given to the call and before any work queued there later; it returns
+ *     once the result is complete (the adaptive r loop reads one counter per
+ *     round of range searches).
  *   - Every function returns a palmad_status.  Arguments are validated on
  *     the host before any device work; on error nothing is written to the
  *     outputs and palmad_last_error() describes the problem.  No C++
  *     exception crosses this interface.
- *   - One context per host thread at a time.
+ *   - One context per host thread at a time.  The context caches the
+ *     hipGraph of one round of the search for the last workspace and
+ *     configuration it saw, and replays it while they stay the same.
  */
 #ifndef PALMAD_H
 #define PALMAD_H
@@ -75,6 +79,9 @@ typedef struct {
    time per kernel class in palmad_stats (adds two event records per timed
    launch). */
 #define PALMAD_FLAG_TIME_KERNELS 1u
+/* Launch every kernel of a round directly instead of replaying the
+   context's cached round graph (set implicitly by PALMAD_FLAG_TIME_KERNELS). */
+#define PALMAD_FLAG_NO_GRAPH 2u
 
 /* Kernel classes of palmad_stats.kernel_* (one entry each). */
 enum {
@@ -150,6 +157,43 @@ int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, i
                     int32_t k, const palmad_options* opts, void* workspace, size_t ws_bytes,
                     int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx, int32_t* count,
                     palmad_stats* stats, void* stream);
+
+/*
+ * Bytes of device workspace palmad_discords_batched() needs.  Pure host
+ * computation; the arguments are those of palmad_discords_batched(), and
+ * the same argument errors are reported.
+ */
+int palmad_batched_workspace_size(int32_t B, const int64_t* offsets, const int32_t* minL,
+                                  const int32_t* maxL, int32_t k, const palmad_options* opts,
+                                  size_t* bytes);
+
+/*
+ * palmad_discords() over B independent series at once (not in the paper: a
+ * serving form of Alg. 1).  Every series runs its own MERLIN walk over its
+ * own lengths with its own r; one round performs one range search for every
+ * series that still has work, in shared launches, so the device stays full
+ * even when single series are too short to fill it.  Results equal B
+ * separate palmad_discords() calls.
+ *
+ *   values   device, float64[offsets[B]]: the series back to back; series b
+ *            is values[offsets[b] .. offsets[b+1]).
+ *   offsets  host, int64[B+1], offsets[0] = 0, non-decreasing.
+ *   minL, maxL  host, int32[B]: the length range of each series; each
+ *            series must satisfy the conditions of palmad_workspace_size().
+ *   k        top-k of every series and length (1..64).
+ *   idx, len, nn_dist, nn_idx  device, sum_b L_b*k rows, L_b = maxL[b] -
+ *            minL[b] + 1: the rows of series b follow those of series b-1,
+ *            each block laid out as in palmad_discords().
+ *   count    device, int32[sum_b L_b], blocks in series order.
+ *   stats    host, optional: counters summed over the batch.
+ * PALMAD_ENONFINITE if any series holds NaN/Inf (the message names the first);
+ * PALMAD_EUNSUPPORTED for B > 65535.
+ */
+int palmad_discords_batched(palmad_ctx* ctx, const double* values, const int64_t* offsets,
+                            int32_t B, const int32_t* minL, const int32_t* maxL, int32_t k,
+                            const palmad_options* opts, void* workspace, size_t ws_bytes,
+                            int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx,
+                            int32_t* count, palmad_stats* stats, void* stream);
 
 /*
  * One range search at a single length m and range r (the DRAG problem of

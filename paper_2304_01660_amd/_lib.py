@@ -62,6 +62,7 @@ class Stats(ctypes.Structure):
 
 
 FLAG_TIME_KERNELS = 1
+FLAG_NO_GRAPH = 2
 KERNEL_CLASSES = ("select_near", "select_far", "refine", "polish")
 
 
@@ -86,6 +87,12 @@ SIGNATURES = {
     "palmad_discords": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32, ctypes.POINTER(Options),
                                        _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
                                        ctypes.POINTER(Stats), _vp]),
+    "palmad_batched_workspace_size": (ctypes.c_int, [_i32, _vp, _vp, _vp, _i32,
+                                                     ctypes.POINTER(Options),
+                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "palmad_discords_batched": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32,
+                                               ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
+                                               _vp, _vp, _vp, _vp, ctypes.POINTER(Stats), _vp]),
     "palmad_range_discords": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.c_double,
                                              ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
                                              _vp, ctypes.POINTER(_i64), ctypes.POINTER(Stats),
@@ -123,7 +130,7 @@ def check(rc: int, ctx=None):
 
 
 def make_options(dist_bits=0, guard=0.0, near_cols=0, chunk_cols=0, time_kernels=False,
-                 rows_near=0, rows_far=0, rows_refine=0, far_grid=0) -> Options:
+                 rows_near=0, rows_far=0, rows_refine=0, far_grid=0, graphs=True) -> Options:
     o = Options()
     o.far_grid = int(far_grid)
     o.rows_near = int(rows_near)
@@ -133,5 +140,5 @@ def make_options(dist_bits=0, guard=0.0, near_cols=0, chunk_cols=0, time_kernels
     o.guard = float(guard)
     o.near_cols = int(near_cols)
     o.chunk_cols = int(chunk_cols)
-    o.flags = FLAG_TIME_KERNELS if time_kernels else 0
+    o.flags = (FLAG_TIME_KERNELS if time_kernels else 0) | (0 if graphs else FLAG_NO_GRAPH)
     return o

@@ -61,7 +61,7 @@ def _workspace(nbytes: int, dev) -> torch.Tensor:
 def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
              guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0, workspace=None,
              return_stats: bool = False, time_kernels: bool = False, rows_near: int = 0,
-             rows_far: int = 0, rows_refine: int = 0, far_grid: int = 0):
+             rows_far: int = 0, rows_refine: int = 0, far_grid: int = 0, graphs: bool = True):
     """Top-k discords of every length in [minL, maxL].
 
     Returns a dict of device tensors: idx int64[L*k], len int32[L*k],
@@ -73,7 +73,7 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
     n = T.shape[0]
     L = maxL - minL + 1
     o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
-                          rows_far, rows_refine, far_grid)
+                          rows_far, rows_refine, far_grid, graphs)
     nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
                             near_cols=near_cols, chunk_cols=chunk_cols)
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
@@ -98,6 +98,94 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
     if return_stats:
         out["stats"] = st.as_dict()
     return out
+
+
+def batched_workspace_size(lengths, minL, maxL, k: int, **opts) -> int:
+    """Workspace bytes of discords_batched for series of the given lengths."""
+    B = len(lengths)
+    offs = (ctypes.c_int64 * (B + 1))()
+    for b, n in enumerate(lengths):
+        offs[b + 1] = offs[b] + int(n)
+    lo = (ctypes.c_int32 * B)(*[int(v) for v in minL])
+    hi = (ctypes.c_int32 * B)(*[int(v) for v in maxL])
+    o = _lib.make_options(**opts)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_batched_workspace_size(B, offs, lo, hi, int(k), ctypes.byref(o),
+                                                        ctypes.byref(nbytes)))
+    return int(nbytes.value)
+
+
+def discords_batched(series, minL, maxL, k: int, *, dist_bits: int = 0, guard: float = 0.0,
+                     near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False,
+                     time_kernels: bool = False, rows_near: int = 0, rows_far: int = 0,
+                     rows_refine: int = 0, far_grid: int = 0, graphs: bool = True,
+                     workspace=None):
+    """Top-k discords of every length of several series in one search.
+
+    ``series`` is a list of 1-D GPU tensors (or one flat tensor plus
+    ``offsets`` given as a list of lengths via a (values, lengths) tuple);
+    ``minL``/``maxL`` are ints or per-series sequences.  Returns a list with
+    one dict per series, laid out as the result of :func:`discords`.
+    """
+    if isinstance(series, tuple):
+        values, lengths = series
+        values = _series(values)
+        lengths = [int(v) for v in lengths]
+    else:
+        parts = [_series(t) for t in series]
+        if not parts:
+            raise ValueError("no series given")
+        values = torch.cat(parts) if len(parts) > 1 else parts[0]
+        lengths = [int(t.shape[0]) for t in parts]
+    dev = values.device
+    B = len(lengths)
+    lo = [int(minL)] * B if isinstance(minL, int) else [int(v) for v in minL]
+    hi = [int(maxL)] * B if isinstance(maxL, int) else [int(v) for v in maxL]
+    if len(lo) != B or len(hi) != B:
+        raise ValueError("minL and maxL need one entry per series")
+    offs = (ctypes.c_int64 * (B + 1))()
+    for b, n in enumerate(lengths):
+        offs[b + 1] = offs[b] + n
+    if offs[B] != values.shape[0]:
+        raise ValueError("series lengths do not add up to the values")
+    c_lo = (ctypes.c_int32 * B)(*lo)
+    c_hi = (ctypes.c_int32 * B)(*hi)
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
+                          rows_far, rows_refine, far_grid, graphs)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_batched_workspace_size(B, offs, c_lo, c_hi, int(k),
+                                                        ctypes.byref(o), ctypes.byref(nbytes)))
+    nbytes = int(nbytes.value)
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace has {ws.numel()} bytes, needs {nbytes}")
+    Ls = [h - l + 1 for l, h in zip(lo, hi)]
+    rows = sum(Ls) * k
+    idx = torch.empty(rows, dtype=torch.int64, device=dev)
+    ln = torch.empty(rows, dtype=torch.int32, device=dev)
+    nn = torch.empty(rows, dtype=torch.float64, device=dev)
+    nnj = torch.empty(rows, dtype=torch.int64, device=dev)
+    cnt = torch.empty(sum(Ls), dtype=torch.int32, device=dev)
+    st = _lib.Stats()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_discords_batched(
+        ctx, ctypes.c_void_p(values.data_ptr()), offs, B, c_lo, c_hi, int(k), ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(idx.data_ptr()),
+        ctypes.c_void_p(ln.data_ptr()), ctypes.c_void_p(nn.data_ptr()),
+        ctypes.c_void_p(nnj.data_ptr()), ctypes.c_void_p(cnt.data_ptr()), ctypes.byref(st),
+        _stream(dev))
+    _lib.check(rc, ctx)
+    res = []
+    r0 = c0 = 0
+    for L in Ls:
+        res.append({"idx": idx[r0:r0 + L * k], "len": ln[r0:r0 + L * k],
+                    "nn_dist": nn[r0:r0 + L * k], "nn_idx": nnj[r0:r0 + L * k],
+                    "count": cnt[c0:c0 + L]})
+        r0 += L * k
+        c0 += L
+    if return_stats:
+        return res, st.as_dict()
+    return res
 
 
 def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, guard: float = 0.0,

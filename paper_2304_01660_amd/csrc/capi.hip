@@ -1,10 +1,12 @@
 // C ABI of the range-discord library (declared in include/palmad.h).
 //
-// Host side only: argument validation, workspace carving and the MERLIN
-// driver loop (Alg. 1) over the lengths.  Each range search (one DRAG call of
-// Alg. 2, parallelised as in Sec. 3.2-3.3) is a fixed sequence of kernel
-// launches on the caller's stream; the driver reads one device flag per
-// search to learn whether the length produced k discords.
+// Host side only: argument validation, workspace planning and the MERLIN
+// driver loop (Alg. 1).  Every search runs the same engine over a batch of
+// series (one series for the plain entry points): per round, every series
+// with work left performs one range search (one DRAG call of Alg. 2,
+// parallelised as in Sec. 3.2-3.3) at its own length.  The driver replays
+// the round as a hipGraph on the context's stream and reads one counter per
+// round to learn whether any series still has work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/palmad.h"
 #include "engine.h"
@@ -23,9 +26,14 @@ using namespace palmad;
 struct palmad_ctx {
     int device;
     std::string err;
-    int32_t* pinned;  // host-pinned flag mirror
-    hipEvent_t ev[KCLASSES][2];
+    int32_t* pinned;             // pinned host mirror of small device counters
+    hipStream_t work;            // the library's stream (default priority)
+    hipEvent_t ev_in, ev_out;    // order the work stream after / before the caller's
+    hipEvent_t ev[KCLASSES][2];  // per-kernel timing
     bool have_events;
+    hipGraph_t graph;            // cached round graph
+    hipGraphExec_t graph_exec;
+    std::string graph_key;
 };
 
 namespace {
@@ -62,11 +70,13 @@ struct Opts {
     int far_grid;
 };
 
+constexpr unsigned int KNOWN_FLAGS = PALMAD_FLAG_TIME_KERNELS | PALMAD_FLAG_NO_GRAPH;
+
 int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 {
     Opts r = {32, 1e-4f, 2048, 1024, 0u, 0, 0, 0, 2048};
     if (o) {
-        if (o->flags & ~PALMAD_FLAG_TIME_KERNELS)
+        if (o->flags & ~KNOWN_FLAGS)
             return fail(ctx, PALMAD_EINVAL, "unknown option flags 0x%x", o->flags);
         r.flags = o->flags;
         const int32_t rows[3] = {o->rows_near, o->rows_far, o->rows_refine};
@@ -103,6 +113,7 @@ int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 // Largest length whose LDS staging (two centred windows + padding, FP64)
 // fits a 64 KiB workgroup allocation.
 constexpr int32_t MAXL_LIMIT = 3000;
+constexpr int32_t B_LIMIT = 65535;
 
 int validate(palmad_ctx* ctx, int64_t n, int32_t minL, int32_t maxL, int32_t k)
 {
@@ -124,6 +135,25 @@ int validate(palmad_ctx* ctx, int64_t n, int32_t minL, int32_t maxL, int32_t k)
     return PALMAD_OK;
 }
 
+int validate_batch(palmad_ctx* ctx, int32_t B, const int64_t* offsets, const int32_t* minL,
+                   const int32_t* maxL, int32_t k, std::vector<int64_t>* n)
+{
+    if (B < 1) return fail(ctx, PALMAD_EINVAL, "B must be >= 1 (got %d)", B);
+    if (B > B_LIMIT) return fail(ctx, PALMAD_EUNSUPPORTED, "B (%d) above %d", B, B_LIMIT);
+    if (!offsets || !minL || !maxL) return fail(ctx, PALMAD_EINVAL, "null offsets, minL or maxL");
+    if (offsets[0] != 0) return fail(ctx, PALMAD_EINVAL, "offsets[0] must be 0");
+    n->resize(B);
+    for (int b = 0; b < B; ++b) {
+        (*n)[b] = offsets[b + 1] - offsets[b];
+        const int rc = validate(ctx, (*n)[b], minL[b], maxL[b], k);
+        if (rc) {
+            const std::string m = ctx ? ctx->err : g_err;
+            return fail(ctx, rc, "series %d: %s", b, m.c_str());
+        }
+    }
+    return PALMAD_OK;
+}
+
 SweepCfg cfg_of(const Opts& o, const KernelTimer* timer)
 {
     SweepCfg c;
@@ -142,6 +172,94 @@ SweepCfg cfg_of(const Opts& o, const KernelTimer* timer)
     return c;
 }
 
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace plan of a batch: descriptors, prefix tables and counters, then
+// one region per series.
+struct Plan {
+    int B;
+    std::vector<Layout> lay;
+    std::vector<size_t> base;
+    size_t off_pfx, off_rem, off_sums, total;
+    int64_t totals[PFX_KINDS];
+    std::vector<int64_t> pfx;  // [PFX_KINDS][B+1]
+    int32_t maxL_all;
+};
+
+void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL, int32_t k,
+               const SweepCfg& cfg, Plan* p)
+{
+    p->B = B;
+    p->lay.resize(B);
+    p->base.resize(B);
+    p->off_pfx = al256(sizeof(SeriesDev) * (size_t)B);
+    p->off_rem = al256(p->off_pfx + sizeof(int64_t) * (size_t)PFX_KINDS * (size_t)(B + 1));
+    p->off_sums = p->off_rem + 64;
+    size_t o = al256(p->off_sums + 8 * sizeof(unsigned long long));
+    p->pfx.assign((size_t)PFX_KINDS * (B + 1), 0);
+    p->maxL_all = 0;
+    for (int b = 0; b < B; ++b) {
+        make_layout(n[b], minL[b], maxL[b], k, &p->lay[b]);
+        p->base[b] = o;
+        o = al256(o + p->lay[b].total);
+        int64_t blk[PFX_KINDS];
+        series_blocks(p->lay[b], cfg, blk);
+        for (int q = 0; q < PFX_KINDS; ++q)
+            p->pfx[(size_t)q * (B + 1) + b + 1] = p->pfx[(size_t)q * (B + 1) + b] + blk[q];
+        p->maxL_all = std::max(p->maxL_all, maxL[b]);
+    }
+    for (int q = 0; q < PFX_KINDS; ++q) p->totals[q] = p->pfx[(size_t)q * (B + 1) + B];
+    p->total = o;
+}
+
+int check_grid(palmad_ctx* ctx, const Plan& p)
+{
+    for (int q = 0; q < PFX_KINDS; ++q)
+        if (p.totals[q] > 0x7fffffffll)
+            return fail(ctx, PALMAD_EUNSUPPORTED, "batch too large: %lld workgroups in one launch",
+                        (long long)p.totals[q]);
+    return PALMAD_OK;
+}
+
+struct Outputs {
+    int64_t* idx;
+    int32_t* len;
+    double* nn;
+    int64_t* nnidx;
+    int32_t* count;
+};
+
+// Write the descriptors and prefix tables into the workspace (one upload).
+int upload(palmad_ctx* ctx, const Plan& p, void* ws, const double* const* Tin, const Outputs* outs,
+           Batch* bt)
+{
+    std::vector<char> blob(p.off_rem, 0);
+    SeriesDev* d = (SeriesDev*)blob.data();
+    for (int b = 0; b < p.B; ++b) {
+        SeriesDev s = carve((char*)ws + p.base[b], p.lay[b]);
+        s.Tin = Tin[b];
+        if (outs) {
+            s.idx = outs[b].idx;
+            s.len = outs[b].len;
+            s.nn = outs[b].nn;
+            s.nnidx = outs[b].nnidx;
+            s.count = outs[b].count;
+        }
+        d[b] = s;
+    }
+    std::memcpy(blob.data() + p.off_pfx, p.pfx.data(), sizeof(int64_t) * p.pfx.size());
+    HIP_TRY(hipMemcpyAsync(ws, blob.data(), blob.size(), hipMemcpyHostToDevice, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    bt->s = (SeriesDev*)ws;
+    for (int q = 0; q < PFX_KINDS; ++q)
+        bt->pfx[q] = (const int64_t*)((char*)ws + p.off_pfx) + (size_t)q * (p.B + 1);
+    bt->B = p.B;
+    bt->maxL_all = p.maxL_all;
+    bt->remaining = (int32_t*)((char*)ws + p.off_rem);
+    bt->sums = (unsigned long long*)((char*)ws + p.off_sums);
+    return PALMAD_OK;
+}
+
 KernelTimer make_timer(palmad_ctx* ctx, const Opts& o)
 {
     KernelTimer t = {};
@@ -153,11 +271,11 @@ KernelTimer make_timer(palmad_ctx* ctx, const Opts& o)
     return t;
 }
 
-// After a synchronised round: add the device time of every class launched.
-int accumulate(palmad_ctx* ctx, KernelTimer& t, int nclasses)
+// After a synchronised round: add the device time of every kernel class.
+int accumulate(palmad_ctx* ctx, KernelTimer& t)
 {
     if (!t.on) return PALMAD_OK;
-    for (int k = 0; k < nclasses; ++k) {
+    for (int k = 0; k < KCLASSES; ++k) {
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, t.ev[k][0], t.ev[k][1]));
         t.ms[k] += ms;
@@ -166,45 +284,113 @@ int accumulate(palmad_ctx* ctx, KernelTimer& t, int nclasses)
     return PALMAD_OK;
 }
 
-int check_ws(palmad_ctx* ctx, void* ws, size_t ws_bytes, const Layout& lay)
+// Order the library's stream after the caller's pending work.
+int enter(palmad_ctx* ctx, void* stream)
 {
-    if (!ws) return fail(ctx, PALMAD_EINVAL, "workspace is NULL");
-    if (((uintptr_t)ws & 255u) != 0) return fail(ctx, PALMAD_EINVAL, "workspace not 256-byte aligned");
-    if (ws_bytes < lay.total)
-        return fail(ctx, PALMAD_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,
-                    lay.total);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipEventRecord(ctx->ev_in, (hipStream_t)stream));
+    HIP_TRY(hipStreamWaitEvent(ctx->work, ctx->ev_in, 0));
     return PALMAD_OK;
 }
 
-// Copy the series, check finiteness and compute the flat-window threshold.
-int prepare(palmad_ctx* ctx, const Layout& lay, const Buffers& b, const double* T, hipStream_t st)
+// Order the caller's stream after the library's work.
+int leave(palmad_ctx* ctx, void* stream)
 {
-    HIP_TRY(launch_prepare(lay, b, T, st));
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, &b.ctrl->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (*ctx->pinned) return fail(ctx, PALMAD_ENONFINITE, "the series holds NaN or Inf values");
+    HIP_TRY(hipEventRecord(ctx->ev_out, ctx->work));
+    HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, ctx->ev_out, 0));
     return PALMAD_OK;
 }
 
-int read_stats(palmad_ctx* ctx, const Buffers& b, palmad_stats* stats, double secs,
-               const KernelTimer& t, hipStream_t st)
+// Padded copies, finiteness check and the flat-window threshold.
+int prepare(palmad_ctx* ctx, const Batch& bt, const Plan& p)
+{
+    HIP_TRY(launch_prepare(bt, p.totals, ctx->work));
+    HIP_TRY(launch_nonfinite(bt, bt.remaining, ctx->work));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, bt.remaining, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    if (ctx->pinned[0]) {
+        if (p.B == 1) return fail(ctx, PALMAD_ENONFINITE, "the series holds NaN or Inf values");
+        return fail(ctx, PALMAD_ENONFINITE, "%d series hold NaN or Inf values (first: series %d)",
+                    ctx->pinned[0], ctx->pinned[1]);
+    }
+    return PALMAD_OK;
+}
+
+std::string graph_key(const Batch& bt, const SweepCfg& c, const Plan& p)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%a|", (void*)bt.s, bt.B, bt.maxL_all,
+             c.near_cols, c.chunk_cols, c.dist_bits, c.far_grid, c.q_near, c.q_far, c.q_ref,
+             (double)c.guard);
+    std::string k = buf;
+    for (int q = 0; q < PFX_KINDS; ++q) k += std::to_string(p.totals[q]) + ",";
+    return k;
+}
+
+void drop_graph(palmad_ctx* ctx)
+{
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+}
+
+// One round: replayed from the context's cached graph (captured on first use
+// for this workspace and configuration), or launched directly.
+int run_round(palmad_ctx* ctx, const Batch& bt, const SweepCfg& cfg, const Plan& p, bool graphs)
+{
+    if (!graphs) {
+        HIP_TRY(launch_round(bt, cfg, p.totals, ctx->work));
+        return PALMAD_OK;
+    }
+    const std::string key = graph_key(bt, cfg, p);
+    if (ctx->graph_exec == nullptr || ctx->graph_key != key) {
+        drop_graph(ctx);
+        HIP_TRY(hipStreamBeginCapture(ctx->work, hipStreamCaptureModeThreadLocal));
+        const hipError_t e = launch_round(bt, cfg, p.totals, ctx->work);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(ctx->work, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(ctx, PALMAD_EDEVICE, "round capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        ctx->graph = g;
+        const hipError_t e3 = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) {
+            ctx->graph_exec = nullptr;
+            drop_graph(ctx);
+            return fail(ctx, PALMAD_EDEVICE, "round graph instantiation failed: %s",
+                        hipGetErrorString(e3));
+        }
+        ctx->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->graph_exec, ctx->work));
+    return PALMAD_OK;
+}
+
+int gather_stats(palmad_ctx* ctx, const Batch& bt, const KernelTimer& t, double secs,
+                 palmad_stats* stats)
 {
     if (!stats) return PALMAD_OK;
-    Ctrl h;
-    HIP_TRY(hipMemcpyAsync(&h, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(launch_sum_stats(bt, bt.sums, ctx->work));
+    unsigned long long* h = (unsigned long long*)(ctx->pinned + 16);
+    HIP_TRY(hipMemcpyAsync(h, bt.sums, 7 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
     std::memset(stats, 0, sizeof *stats);
-    stats->evals_select = h.evals_sel;
-    stats->evals_refine = h.evals_ref;
-    stats->evals_polish = h.evals_pol;
-    stats->range_searches = h.rounds;
-    stats->survivors = h.survivors;
+    stats->evals_select = h[0];
+    stats->evals_refine = h[1];
+    stats->evals_polish = h[2];
+    stats->range_searches = h[3];
+    stats->survivors = h[4];
+    stats->kernel_evals[PALMAD_KERNEL_SELECT_NEAR] = h[5];
+    stats->kernel_evals[PALMAD_KERNEL_SELECT_FAR] = h[6];
+    stats->kernel_evals[PALMAD_KERNEL_REFINE] = h[1];
+    stats->kernel_evals[PALMAD_KERNEL_POLISH] = h[2];
     stats->seconds = secs;
-    stats->kernel_evals[PALMAD_KERNEL_SELECT_NEAR] = h.evals_near;
-    stats->kernel_evals[PALMAD_KERNEL_SELECT_FAR] = h.evals_far;
-    stats->kernel_evals[PALMAD_KERNEL_REFINE] = h.evals_ref;
-    stats->kernel_evals[PALMAD_KERNEL_POLISH] = h.evals_pol;
     for (int k = 0; k < KCLASSES; ++k) {
         stats->kernel_launches[k] = t.launches[k];
         stats->kernel_ms[k] = t.ms[k];
@@ -212,11 +398,75 @@ int read_stats(palmad_ctx* ctx, const Buffers& b, palmad_stats* stats, double se
     return PALMAD_OK;
 }
 
+// MERLIN over a batch (Alg. 1 per series): rounds until no series has work.
+int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double* const* Tin,
+           const Outputs* outs, palmad_stats* stats, void* stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    KernelTimer timer = make_timer(ctx, o);
+    const SweepCfg cfg = cfg_of(o, &timer);
+    int rc = enter(ctx, stream);
+    if (rc) return rc;
+    Batch bt;
+    rc = upload(ctx, p, ws, Tin, outs, &bt);
+    if (rc) return rc;
+    rc = prepare(ctx, bt, p);
+    if (rc) return rc;
+    const bool graphs = !timer.on && !(o.flags & PALMAD_FLAG_NO_GRAPH);
+    int64_t max_rounds = 0;
+    for (int b = 0; b < p.B; ++b) max_rounds = std::max<int64_t>(max_rounds, p.lay[b].L);
+    max_rounds = max_rounds * MAX_ATTEMPTS + 2;
+    for (int64_t round = 0;; ++round) {
+        if (round > max_rounds) return fail(ctx, PALMAD_EDEVICE, "search did not terminate");
+        rc = run_round(ctx, bt, cfg, p, graphs);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, bt.remaining, 2 * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, ctx->work));
+        HIP_TRY(hipStreamSynchronize(ctx->work));
+        rc = accumulate(ctx, timer);
+        if (rc) return rc;
+        if (ctx->pinned[1])
+            return fail(ctx, PALMAD_EDEVICE,
+                        "%d series: a range search did not converge within %d attempts",
+                        ctx->pinned[1], MAX_ATTEMPTS);
+        if (ctx->pinned[0] == 0) break;
+    }
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rc = gather_stats(ctx, bt, timer, secs, stats);
+    if (rc) return rc;
+    return leave(ctx, stream);
+}
+
+int check_ws(palmad_ctx* ctx, void* ws, size_t ws_bytes, size_t need)
+{
+    if (!ws) return fail(ctx, PALMAD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(ctx, PALMAD_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(ctx, PALMAD_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return PALMAD_OK;
+}
+
+Opts default_opts()
+{
+    Opts o;
+    read_opts(nullptr, nullptr, &o);
+    return o;
+}
+
+// Backward workspace: a one-series plan at length maxm, then the partials.
+size_t backward_bytes(int64_t n, int64_t K, int32_t maxm, Plan* p, int64_t* nblk)
+{
+    make_plan(1, &n, &maxm, &maxm, 1, cfg_of(default_opts(), nullptr), p);
+    *nblk = (n + 255) / 256;
+    return p->total + al256((size_t)std::max<int64_t>(K, 1) * (size_t)*nblk * 2 * sizeof(double));
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* palmad_version(void) { return "palmad-mi355x 0.1 (gfx950)"; }
+const char* palmad_version(void) { return "palmad-mi355x 0.2 (gfx950)"; }
 
 const char* palmad_last_error(const palmad_ctx* ctx)
 {
@@ -241,10 +491,20 @@ int palmad_create(palmad_ctx** out, int device)
     if (!ctx) return fail(nullptr, PALMAD_ENOMEM, "context allocation failed");
     ctx->device = device;
     ctx->pinned = nullptr;
-    e = hipHostMalloc((void**)&ctx->pinned, 64, hipHostMallocDefault);
+    ctx->work = nullptr;
+    ctx->ev_in = ctx->ev_out = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_exec = nullptr;
+    e = hipHostMalloc((void**)&ctx->pinned, 256, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+        if (ctx->work) (void)hipStreamDestroy(ctx->work);
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         delete ctx;
-        return fail(nullptr, PALMAD_EDEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
+        return fail(nullptr, PALMAD_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
     }
     ctx->have_events = true;
     for (int k = 0; k < KCLASSES; ++k)
@@ -258,28 +518,30 @@ void palmad_destroy(palmad_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    (void)hipStreamSynchronize(ctx->work);
+    drop_graph(ctx);
     if (ctx->have_events)
         for (int k = 0; k < KCLASSES; ++k)
             for (int q = 0; q < 2; ++q) (void)hipEventDestroy(ctx->ev[k][q]);
+    (void)hipEventDestroy(ctx->ev_in);
+    (void)hipEventDestroy(ctx->ev_out);
+    (void)hipStreamDestroy(ctx->work);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
 
 int palmad_workspace_size(int64_t n, int32_t minL, int32_t maxL, int32_t k,
                           const palmad_options* opts, size_t* bytes)
 {
-    palmad_ctx* ctx = nullptr;
     if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
     int rc = validate(nullptr, n, minL, maxL, k);
     if (rc) return rc;
     Opts o;
     rc = read_opts(nullptr, opts, &o);
     if (rc) return rc;
-    Layout lay;
-    if (!make_layout(n, minL, maxL, k, o.dist_bits, &lay))
-        return fail(ctx, PALMAD_EINVAL, "layout failed");
-    *bytes = lay.total;
+    Plan p;
+    make_plan(1, &n, &minL, &maxL, k, cfg_of(o, nullptr), &p);
+    *bytes = p.total;
     return PALMAD_OK;
 }
 
@@ -288,7 +550,6 @@ int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, i
                     int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx, int32_t* count,
                     palmad_stats* stats, void* stream)
 {
-    const auto t0 = std::chrono::steady_clock::now();
     if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
     if (!T || !idx || !len || !nn_dist || !nn_idx || !count)
         return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
@@ -297,35 +558,65 @@ int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, i
     Opts o;
     rc = read_opts(ctx, opts, &o);
     if (rc) return rc;
-    Layout lay;
-    make_layout(n, minL, maxL, k, o.dist_bits, &lay);
-    rc = check_ws(ctx, workspace, ws_bytes, lay);
+    Plan p;
+    make_plan(1, &n, &minL, &maxL, k, cfg_of(o, nullptr), &p);
+    rc = check_ws(ctx, workspace, ws_bytes, p.total);
     if (rc) return rc;
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    const Buffers b = carve(workspace, lay);
-    KernelTimer timer = make_timer(ctx, o);
-    const SweepCfg cfg = cfg_of(o, &timer);
-    rc = prepare(ctx, lay, b, T, st);
+    const Outputs out = {idx, len, nn_dist, nn_idx, count};
+    return search(ctx, p, o, workspace, &T, &out, stats, stream);
+}
+
+int palmad_batched_workspace_size(int32_t B, const int64_t* offsets, const int32_t* minL,
+                                  const int32_t* maxL, int32_t k, const palmad_options* opts,
+                                  size_t* bytes)
+{
+    if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
+    std::vector<int64_t> n;
+    int rc = validate_batch(nullptr, B, offsets, minL, maxL, k, &n);
     if (rc) return rc;
-    for (int32_t m = minL; m <= maxL; ++m) {
-        HIP_TRY(launch_stats(lay, b, m, m == minL, st));
-        for (int attempt = 0;; ++attempt) {
-            if (attempt > 5000)
-                return fail(ctx, PALMAD_EDEVICE, "length %d: range search did not converge", m);
-            HIP_TRY(launch_round(lay, b, cfg, m, attempt, st));
-            HIP_TRY(launch_finish_length(lay, b, cfg, m, idx, len, nn_dist, nn_idx, count, st));
-            HIP_TRY(hipMemcpyAsync(ctx->pinned, &b.ctrl->done, sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            rc = accumulate(ctx, timer, KCLASSES);
-            if (rc) return rc;
-            if (*ctx->pinned) break;
-        }
+    Opts o;
+    rc = read_opts(nullptr, opts, &o);
+    if (rc) return rc;
+    Plan p;
+    make_plan(B, n.data(), minL, maxL, k, cfg_of(o, nullptr), &p);
+    rc = check_grid(nullptr, p);
+    if (rc) return rc;
+    *bytes = p.total;
+    return PALMAD_OK;
+}
+
+int palmad_discords_batched(palmad_ctx* ctx, const double* values, const int64_t* offsets,
+                            int32_t B, const int32_t* minL, const int32_t* maxL, int32_t k,
+                            const palmad_options* opts, void* workspace, size_t ws_bytes,
+                            int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx,
+                            int32_t* count, palmad_stats* stats, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!values || !idx || !len || !nn_dist || !nn_idx || !count)
+        return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    std::vector<int64_t> n;
+    int rc = validate_batch(ctx, B, offsets, minL, maxL, k, &n);
+    if (rc) return rc;
+    Opts o;
+    rc = read_opts(ctx, opts, &o);
+    if (rc) return rc;
+    Plan p;
+    make_plan(B, n.data(), minL, maxL, k, cfg_of(o, nullptr), &p);
+    rc = check_grid(ctx, p);
+    if (rc) return rc;
+    rc = check_ws(ctx, workspace, ws_bytes, p.total);
+    if (rc) return rc;
+    std::vector<const double*> tin(B);
+    std::vector<Outputs> outs(B);
+    int64_t row = 0, lrow = 0;
+    for (int b = 0; b < B; ++b) {
+        tin[b] = values + offsets[b];
+        const int64_t L = (int64_t)maxL[b] - minL[b] + 1;
+        outs[b] = {idx + row, len + row, nn_dist + row, nn_idx + row, count + lrow};
+        row += L * k;
+        lrow += L;
     }
-    const double secs =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return read_stats(ctx, b, stats, secs, timer, st);
+    return search(ctx, p, o, workspace, tin.data(), outs.data(), stats, stream);
 }
 
 int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m, double r,
@@ -343,62 +634,70 @@ int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m
     Opts o;
     rc = read_opts(ctx, opts, &o);
     if (rc) return rc;
-    Layout lay;
-    make_layout(n, m, m, 1, o.dist_bits, &lay);
-    rc = check_ws(ctx, workspace, ws_bytes, lay);
-    if (rc) return rc;
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    const Buffers b = carve(workspace, lay);
     KernelTimer timer = make_timer(ctx, o);
     const SweepCfg cfg = cfg_of(o, &timer);
-    rc = prepare(ctx, lay, b, T, st);
+    Plan p;
+    make_plan(1, &n, &m, &m, 1, cfg, &p);
+    rc = check_ws(ctx, workspace, ws_bytes, p.total);
     if (rc) return rc;
-    HIP_TRY(launch_stats(lay, b, m, true, st));
-    HIP_TRY(launch_set_fixed_r(b, r, st));
-    HIP_TRY(launch_round(lay, b, cfg, m, 0, st));
-    HIP_TRY(launch_range_out(lay, b, m, (unsigned long long*)alive, nn_dist, st));
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, &b.ctrl->nsurv, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    *count = (int64_t)(uint32_t)*ctx->pinned;
-    rc = accumulate(ctx, timer, 3);  // no polish in a single range search
+    rc = enter(ctx, stream);
+    if (rc) return rc;
+    Batch bt;
+    rc = upload(ctx, p, workspace, &T, nullptr, &bt);
+    if (rc) return rc;
+    rc = prepare(ctx, bt, p);
+    if (rc) return rc;
+    HIP_TRY(launch_set_fixed_r(bt, r, ctx->work));
+    HIP_TRY(launch_round(bt, cfg, p.totals, ctx->work));
+    const int64_t N = n - m + 1;
+    HIP_TRY(launch_range_out(bt, N, (unsigned long long*)alive, nn_dist, ctx->work));
+    const Ctrl* c = (const Ctrl*)((char*)workspace + p.base[0] + p.lay[0].off_ctrl);
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, &c->nsurv, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    *count = (int64_t)(uint32_t)ctx->pinned[0];
+    rc = accumulate(ctx, timer);
     if (rc) return rc;
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return read_stats(ctx, b, stats, secs, timer, st);
+    rc = gather_stats(ctx, bt, timer, secs, stats);
+    if (rc) return rc;
+    return leave(ctx, stream);
 }
 
-namespace {
-struct BwdLayout {
-    Layout lay;
-    int64_t nblk;
-    size_t off_part, total;
-};
-bool bwd_layout(int64_t n, int64_t K, int32_t maxm, BwdLayout* out)
+int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
+                        void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream)
 {
-    BwdLayout b = {};
-    make_layout(n, maxm, maxm, 1, 64, &b.lay);
-    b.lay.L = 0;  // no length history
-    b.nblk = (n + 255) / 256;
-    b.off_part = b.lay.total;
-    b.total = b.off_part + (((size_t)std::max<int64_t>(K, 1) * (size_t)b.nblk * 2 * sizeof(double) +
-                             255) & ~(size_t)255);
-    *out = b;
-    return true;
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!T || !mu || !sigma) return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    int rc = validate(ctx, n, minL, m, 1);
+    if (rc) return rc;
+    Plan p;
+    make_plan(1, &n, &minL, &m, 1, cfg_of(default_opts(), nullptr), &p);
+    rc = check_ws(ctx, workspace, ws_bytes, p.total);
+    if (rc) return rc;
+    rc = enter(ctx, stream);
+    if (rc) return rc;
+    Batch bt;
+    rc = upload(ctx, p, workspace, &T, nullptr, &bt);
+    if (rc) return rc;
+    rc = prepare(ctx, bt, p);
+    if (rc) return rc;
+    HIP_TRY(launch_stats_to(bt, minL, m, p.totals, ctx->work));
+    HIP_TRY(launch_stats_out(bt, n - m + 1, mu, sigma, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    return leave(ctx, stream);
 }
-}  // namespace
 
 int palmad_backward_workspace_size(int64_t n, int64_t K, int32_t maxm, size_t* bytes)
 {
-    palmad_ctx* ctx = nullptr;
     if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
     if (K < 0) return fail(nullptr, PALMAD_EINVAL, "K must be >= 0");
     int rc = validate(nullptr, n, maxm, maxm, 1);
     if (rc) return rc;
-    BwdLayout b;
-    bwd_layout(n, K, maxm, &b);
-    *bytes = b.total;
-    (void)ctx;
+    Plan p;
+    int64_t nblk;
+    *bytes = backward_bytes(n, K, maxm, &p, &nblk);
     return PALMAD_OK;
 }
 
@@ -414,48 +713,29 @@ int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_
     int rc = validate(ctx, n, maxm, maxm, 1);
     if (rc) return rc;
     if (K > 65535) return fail(ctx, PALMAD_EUNSUPPORTED, "K (%lld) above 65535", (long long)K);
-    BwdLayout bl;
-    bwd_layout(n, K, maxm, &bl);
-    if (!workspace) return fail(ctx, PALMAD_EINVAL, "workspace is NULL");
-    if (((uintptr_t)workspace & 255u) != 0)
-        return fail(ctx, PALMAD_EINVAL, "workspace not 256-byte aligned");
-    if (ws_bytes < bl.total)
-        return fail(ctx, PALMAD_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes,
-                    bl.total);
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    const Buffers b = carve(workspace, bl.lay);
-    rc = prepare(ctx, bl.lay, b, T, st);
+    Plan p;
+    int64_t nblk;
+    const size_t need = backward_bytes(n, K, maxm, &p, &nblk);
+    rc = check_ws(ctx, workspace, ws_bytes, need);
     if (rc) return rc;
-    if (K == 0) return PALMAD_OK;
-    HIP_TRY(launch_set_max_len(b, maxm, st));
-    double* part = (double*)((char*)workspace + bl.off_part);
-    HIP_TRY(launch_adjoint(b.T, n, K, maxm, idx, len, grad_nn, b.ctrl, part, bl.nblk, grad_T,
-                           nn_idx, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return PALMAD_OK;
-}
-
-int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
-                        void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream)
-{
-    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
-    if (!T || !mu || !sigma) return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
-    int rc = validate(ctx, n, minL, m, 1);
+    rc = enter(ctx, stream);
     if (rc) return rc;
-    Layout lay;
-    make_layout(n, minL, m, 1, 32, &lay);
-    rc = check_ws(ctx, workspace, ws_bytes, lay);
+    Batch bt;
+    rc = upload(ctx, p, workspace, &T, nullptr, &bt);
     if (rc) return rc;
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    const Buffers b = carve(workspace, lay);
-    rc = prepare(ctx, lay, b, T, st);
+    rc = prepare(ctx, bt, p);
     if (rc) return rc;
-    for (int32_t mm = minL; mm <= m; ++mm) HIP_TRY(launch_stats(lay, b, mm, mm == minL, st));
-    HIP_TRY(launch_stats_out(lay, b, m, mu, sigma, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return PALMAD_OK;
+    if (K > 0) {
+        // the adjoint reads the largest admissible length and the flat
+        // threshold from the control block
+        HIP_TRY(launch_set_len(bt, maxm, ctx->work));
+        const SeriesDev s = carve((char*)workspace + p.base[0], p.lay[0]);
+        double* part = (double*)((char*)workspace + p.total);
+        HIP_TRY(launch_adjoint(s.T, n, K, maxm, idx, len, grad_nn, s.ctrl, part, nblk, grad_T,
+                               nn_idx, ctx->work));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    return leave(ctx, stream);
 }
 
 }  // extern "C"

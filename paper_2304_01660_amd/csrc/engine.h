@@ -1,5 +1,13 @@
 // Internal interface between the C ABI layer (capi.hip) and the kernels
-// (kernels.hip).  Not installed; the public interface is include/palmad.h.
+// (kernels.hip, prep.hip, adjoint.hip).  Not installed; the public interface
+// is include/palmad.h.
+//
+// The engine searches B series at once (B = 1 for a single series).  Every
+// series carries its own MERLIN state (Alg. 1) in a device-resident control
+// block; one "round" performs one range search (one DRAG call, Alg. 2) for
+// every series that still has work, each at its own length and attempt.  All
+// geometry and state are read from device descriptors, so a round is a fixed
+// sequence of launches that can be captured once in a hipGraph.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,19 +16,18 @@
 
 namespace palmad {
 
-// Row-tile geometry of the sweeps: a tile is one wavefront of 64 lanes, each
-// lane owning Q consecutive rows (subsequence start indices).
 constexpr int WAVE = 64;
-constexpr int R_MAX = 512;
+constexpr int R_MAX = 512;   // tallest row tile (64 lanes x 8 rows)
 constexpr int KP_EXTRA = 4;  // candidates polished beyond k
 constexpr int K_MAX = 64;
 constexpr int KP_MAX = K_MAX + KP_EXTRA;
 constexpr int POLISH_BLOCK = 256;
 constexpr int TOPK_BLOCK = 1024;
 constexpr int RED_BLOCKS = 256;   // series reductions: blocks of 256 threads
+constexpr int MAX_ATTEMPTS = 5000;
 
-// Device-resident control block of one search (the MERLIN state of Alg. 1
-// plus per-round work counters).  Lives in the workspace.
+// Device-resident control block of one series (the MERLIN state of Alg. 1
+// plus the work counters of the current round).
 struct Ctrl {
     // controller
     double r;          // current range (ED units)
@@ -31,14 +38,21 @@ struct Ctrl {
     int32_t mode;      // 0: first length, 1: next four, 2: later lengths, 3: fixed r
     int32_t done;      // 1 once the current length succeeded
     int32_t prune;     // 1 if r > 0
-    int32_t m;
+    int32_t m;         // current length
     int32_t li;        // m - minL
+    int32_t attempt;   // range searches so far at this length
+    int32_t active;    // 1 if the series searches in this round
+    int32_t finished;  // 1 once every length is done (or on error)
+    int32_t started;
+    int32_t new_len;   // 0: same length as last round, 1: update statistics, 2: initialise
+    int32_t error;     // 1: did not converge within MAX_ATTEMPTS
     int32_t nonfinite; // set when the series holds NaN/Inf
     double flat_eps;   // sigma threshold of a flat window
     double sigmaT;     // population sigma of the whole series
     // work lists of the current round
-    uint32_t nlive_sel, maxc_sel, ctr_sel;
-    uint32_t nlive_ref, maxc_ref, ctr_ref;
+    uint32_t nlive_sel, maxc_sel;  // live selection tiles, most chunks of one tile
+    uint32_t nlive_ref, maxc_ref;
+    unsigned long long ctr_sel, ctr_ref;  // work-queue heads (items: chunk-major)
     uint32_t nsurv;
     uint32_t ncand;
     int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
@@ -47,44 +61,70 @@ struct Ctrl {
     unsigned long long evals_near, evals_far;
 };
 
-// Workspace carve-up (all offsets 256-byte aligned).
-struct Layout {
-    int64_t n, Nmax, Npad, Tlen;
-    int32_t minL, maxL, k, L, kp;
-    int32_t dist_bits;
-    size_t off_T, off_mu, off_var, off_h32, off_h64, off_alive, off_rho, off_tsel, off_tref,
-        off_surv, off_cand, off_part, off_hist, off_flat, off_ctrl, off_red, total;
-    int64_t nwords;      // alive bitmap words
-    int64_t npart;       // polish partial slots per candidate
-};
-
-bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, int32_t dist_bits, Layout* out);
-
-// Pointers into a carved workspace.
-struct Buffers {
-    double* T;        // padded FP64 series
-    double* mu;       // [Npad+64]
-    double* var;      // [Npad+64]
-    float* df32;      // helpers, FP32 (3 arrays of Npad+64)
+// Static geometry and buffers of one series (host computes, device reads).
+struct SeriesDev {
+    // geometry
+    int64_t n, Nmax, Npad, Tlen, nwords, npart;
+    int32_t minL, maxL, k, kp, L, pad0;
+    // input and workspace buffers
+    const double* Tin;   // caller's series
+    double* T;           // padded FP64 copy
+    double* mu;          // [Npad+64]
+    double* var;         // [Npad+64]
+    float* df32;         // helpers, FP32 (SoA, Npad+64 each)
     float* dg32;
     float* inv32;
-    double* df64;     // helpers, FP64
+    double* df64;        // helpers, FP64
     double* dg64;
     double* inv64;
     unsigned long long* alive;   // bitmap [nwords]
     unsigned long long* rho;     // ordered-bits row max correlation [Npad]
-    int32_t* tsel;    // live selection tiles
-    int32_t* tref;    // live refinement tiles
-    int32_t* surv;    // survivor rows
-    int64_t* cand;    // polished candidates [KP_MAX]
-    double* part;     // polish partials [KP_MAX * npart * 2]
-    double* hist;     // nnDist history per length [L]
-    int64_t* flat;    // [2]: min, max flat index at current m
+    int32_t* tsel;       // live selection tiles
+    int32_t* tref;       // live refinement tiles
+    int32_t* surv;       // survivor rows
+    int64_t* cand;       // polished candidates [KP_MAX]
+    double* part;        // polish partials [KP_MAX * npart * 2 + tail]
+    double* hist;        // nnDist history per length [L]
+    double* red;         // reduction scratch [2 * RED_BLOCKS]
     Ctrl* ctrl;
-    double* red;      // reduction scratch [2048]
+    // outputs (rows of this series; NULL for a bare range search)
+    int64_t* idx;
+    int32_t* len;
+    double* nn;
+    int64_t* nnidx;
+    int32_t* count;
 };
 
-Buffers carve(void* ws, const Layout& lay);
+// Per-series layout (host side; offsets relative to the series' base).
+struct Layout {
+    int64_t n, Nmax, Npad, Tlen, nwords, npart;
+    int32_t minL, maxL, k, L, kp;
+    size_t off_T, off_mu, off_var, off_h32, off_h64, off_alive, off_rho, off_tsel, off_tref,
+        off_surv, off_cand, off_part, off_hist, off_ctrl, off_red, total;
+};
+bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
+SeriesDev carve(void* base, const Layout& lay);
+
+// Prefix tables mapping a flat block index to (series, local block): entry b
+// is the first flat block of series b; entry B the total.
+enum PrefixKind {
+    PFX_ELEM = 0,   // blocks of 256 over Npad+64 elements (statistics, resets)
+    PFX_NEAR,       // first-pass selection items: tiles x chunks
+    PFX_TSEL,       // blocks of 256 over selection tiles (compaction)
+    PFX_TREF,       // blocks of 256 over refinement tiles (compaction)
+    PFX_WORDS,      // blocks of 256 over bitmap words (survivors)
+    PFX_POLISH,     // blocks of 256 columns (polish)
+    PFX_KINDS
+};
+
+struct Batch {
+    SeriesDev* s;                    // device array [B]
+    const int64_t* pfx[PFX_KINDS];   // device arrays [B+1]
+    int32_t B;
+    int32_t maxL_all;                // largest length over the batch (LDS sizing)
+    int32_t* remaining;              // device [2]: series with work left, series in error
+    unsigned long long* sums;        // device [8]: counters summed over the batch
+};
 
 // Optional per-kernel event timing (host side).
 constexpr int KCLASSES = 4;  // select near, select far, refine, polish
@@ -108,28 +148,43 @@ struct SweepCfg {
     int chunk_cols;
     float guard;
     int dist_bits;
-    int far_grid;     // workgroups of the split passes
+    int far_grid;              // workgroups of the queued passes
     int q_near, q_far, q_ref;  // rows per lane of each pass's tiles (2, 4 or 8)
     const KernelTimer* timer;
 };
 
-// ---- launchers (all asynchronous on `st`) ----
-hipError_t launch_prepare(const Layout& lay, const Buffers& b, const double* T_user, hipStream_t st);
-hipError_t launch_stats(const Layout& lay, const Buffers& b, int32_t m, bool init, hipStream_t st);
-hipError_t launch_round(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                        int attempt, hipStream_t st);
-hipError_t launch_finish_length(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                                int64_t* idx, int32_t* len, double* nn, int64_t* nnidx,
-                                int32_t* count, hipStream_t st);
-hipError_t launch_set_fixed_r(const Buffers& b, double r, hipStream_t st);
-hipError_t launch_range_out(const Layout& lay, const Buffers& b, int32_t m,
-                            unsigned long long* alive_out, double* nn_out, hipStream_t st);
+// Blocks of each prefix kind needed by one series under a configuration.
+void series_blocks(const Layout& lay, const SweepCfg& cfg, int64_t out[PFX_KINDS]);
+
+// ---- launchers (all asynchronous on `st`); `total[kind]` = pfx[kind][B] ----
+hipError_t launch_prepare(const Batch& bt, const int64_t* total, hipStream_t st);
+hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st);
+hipError_t launch_set_fixed_r(const Batch& bt, double r, hipStream_t st);
+hipError_t launch_range_out(const Batch& bt, int64_t N, unsigned long long* alive_out,
+                            double* nn_out, hipStream_t st);
+hipError_t launch_stats_to(const Batch& bt, int32_t minL, int32_t m, const int64_t* total,
+                           hipStream_t st);
+// Per-series counters summed over the batch: 7 values (see k_sum_stats).
+hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_t st);
+// out[0] = series holding NaN/Inf, out[1] = the first of them (or -1).
+hipError_t launch_nonfinite(const Batch& bt, int32_t* out, hipStream_t st);
+hipError_t launch_set_len(const Batch& bt, int32_t m, hipStream_t st);
+hipError_t launch_stats_out(const Batch& bt, int64_t N, double* mu, double* sigma, hipStream_t st);
 hipError_t launch_adjoint(const double* Tpad, int64_t n, int64_t K, int32_t maxm,
                           const int64_t* idx, const int32_t* len, const double* gin,
                           const Ctrl* ctrl, double* part, int64_t nblk, double* grad,
                           int64_t* jstar, hipStream_t st);
-hipError_t launch_set_max_len(const Buffers& b, int32_t maxm, hipStream_t st);
-hipError_t launch_stats_out(const Layout& lay, const Buffers& b, int32_t m, double* mu,
-                            double* sigma, hipStream_t st);
+
+// Device helper: series owning flat block `blk` (binary search over pfx).
+__device__ __forceinline__ int series_of(const int64_t* pfx, int B, int64_t blk)
+{
+    int lo = 0, hi = B;  // pfx[lo] <= blk < pfx[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pfx[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 }  // namespace palmad

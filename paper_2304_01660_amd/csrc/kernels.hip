@@ -20,12 +20,18 @@
 //     into the next lane.  Lane 0's top row is taken from exact FP64 dot
 //     products computed 64 columns at a time, so every value is at most R
 //     recurrence steps from an exact one.
-//   * Column helpers (df, dg, 1/(sqrt(m) sigma)) are wave-uniform per step
-//     and come through scalar loads.
+//   * Each block of 64 columns is staged in LDS with one burst of loads: the
+//     T segment (for the boundary dot products) and, per step, the column
+//     helpers df, dg, 1/(sqrt(m) sigma) and the boundary value, all read as
+//     one broadcast record.
 //   * Row and column prunes are lane masks; a column prune is one ballot per
 //     step, flushed to the candidate bitmap every 64 columns with one atomic.
 //   * Long scans are split into column chunks fed from a device work list in
 //     nearest-first order, so the critical path is one chunk, not one row.
+//   * Every kernel serves a batch of series: flat block indices map to
+//     (series, block) through host-built prefix tables, the queued passes
+//     drain each series' work list in turn, and all per-series geometry and
+//     MERLIN state is read from device descriptors.
 #include "engine.h"
 
 #include <math.h>
@@ -150,133 +156,173 @@ __device__ __forceinline__ unsigned long long pair_count(long long ilo, long lon
 }
 
 // ---------------------------------------------------------------------------
-// per-length statistics (Eq. (4) at minL, Eq. (7)-(8) after) and helpers
+// round preparation: MERLIN's walk over the lengths (Alg. 1)
 // ---------------------------------------------------------------------------
-__global__ void k_stats_init(const double* __restrict__ T, int64_t n, int32_t m, int64_t len,
-                             double* __restrict__ mu, double* __restrict__ var, Ctrl* ctrl)
+// Advance every series: the first round starts at minL; after a successful
+// round the next length starts; after a failed one the same length is
+// searched again with the r that k_round_end lowered.
+__global__ void k_round_prep(SeriesDev* S, int B)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        ctrl->flat_min = 0x7fffffffffffffffll;
-        ctrl->flat_max = -1;
-    }
-    if (i >= len) return;
-    const int64_t N = n - m + 1;
-    if (i >= N) {
-        mu[i] = 0.0;
-        var[i] = 0.0;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (c->finished) {
+        c->active = 0;
         return;
     }
-    double s = 0.0;
-    for (int k = 0; k < m; ++k) s += T[i + k];
-    const double mean = s / (double)m;
-    double q = 0.0;
-    for (int k = 0; k < m; ++k) {
-        const double d = T[i + k] - mean;
-        q += d * d;
+    if (!c->started) {
+        c->started = 1;
+        c->m = s.minL;
+        c->li = 0;
+        c->attempt = 0;
+        c->new_len = 2;
+        c->done = 0;
+        c->active = 1;
+        return;
     }
-    mu[i] = mean;
-    var[i] = q / (double)m;
+    if (c->done) {
+        if (c->m >= s.maxL) {
+            c->finished = 1;
+            c->active = 0;
+            return;
+        }
+        c->m += 1;
+        c->li += 1;
+        c->attempt = 0;
+        c->new_len = 1;
+        c->done = 0;
+    } else {
+        c->attempt += 1;
+        c->new_len = 0;
+        if (c->attempt >= MAX_ATTEMPTS) {
+            c->error = 1;
+            c->finished = 1;
+            c->active = 0;
+            return;
+        }
+    }
+    c->active = 1;
 }
 
-// Statistics of length m+1 from length m, in place (Eq. (7)-(8)).
-__global__ void k_stats_update(const double* __restrict__ T, int64_t n, int32_t m, int64_t len,
-                               double* __restrict__ mu, double* __restrict__ var, Ctrl* ctrl)
+// ---------------------------------------------------------------------------
+// per-length statistics (Eq. (4) at minL, Eq. (7)-(8) after) and helpers
+// ---------------------------------------------------------------------------
+__global__ void k_stats(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active || c->new_len == 0) return;
+    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
     if (i == 0) {
-        ctrl->flat_min = 0x7fffffffffffffffll;
-        ctrl->flat_max = -1;
+        c->flat_min = 0x7fffffffffffffffll;
+        c->flat_max = -1;
     }
-    if (i >= len) return;
-    const int64_t N1 = n - m;  // windows of length m+1
-    if (i >= N1) {
-        mu[i] = 0.0;
-        var[i] = 0.0;
-        return;
+    if (i >= s.Npad + 64) return;
+    const double* __restrict__ T = s.T;
+    const int32_t m = c->m;
+    if (c->new_len == 2) {
+        // Eq. (4): direct two-pass statistics at the first length
+        const int64_t N = s.n - m + 1;
+        if (i >= N) {
+            s.mu[i] = 0.0;
+            s.var[i] = 0.0;
+            return;
+        }
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) acc += T[i + k];
+        const double mean = acc / (double)m;
+        double q = 0.0;
+        for (int k = 0; k < m; ++k) {
+            const double d = T[i + k] - mean;
+            q += d * d;
+        }
+        s.mu[i] = mean;
+        s.var[i] = q / (double)m;
+    } else {
+        // Eq. (7)-(8): length m from length m-1, in place
+        const int32_t mo = m - 1;
+        const int64_t N1 = s.n - mo;  // windows of length m
+        if (i >= N1) {
+            s.mu[i] = 0.0;
+            s.var[i] = 0.0;
+            return;
+        }
+        const double t = T[i + mo];
+        const double mu0 = s.mu[i];
+        const double dm = (double)mo;
+        const double d = mu0 - t;
+        s.mu[i] = (dm * mu0 + t) / (dm + 1.0);
+        s.var[i] = dm / (dm + 1.0) * (s.var[i] + d * d / (dm + 1.0));
     }
-    const double t = T[i + m];
-    const double mo = mu[i];
-    const double dm = (double)m;
-    const double d = mo - t;
-    mu[i] = (dm * mo + t) / (dm + 1.0);
-    var[i] = dm / (dm + 1.0) * (var[i] + d * d / (dm + 1.0));
 }
 
 // df[i] = (t_{i+m} - t_i)/2, dg[i] = (t_{i+m} - mu_{i+1}) + (t_i - mu_i) for
 // i < N-1 (zero beyond), inv[i] = 1/(sqrt(m) sigma_i) for non-flat i < N.
-__global__ void k_helpers(const double* __restrict__ T, int64_t n, int32_t m, int64_t len,
-                          const double* __restrict__ mu, const double* __restrict__ var,
-                          float* __restrict__ df32, float* __restrict__ dg32,
-                          float* __restrict__ inv32, double* __restrict__ df64,
-                          double* __restrict__ dg64, double* __restrict__ inv64, Ctrl* ctrl)
+__global__ void k_helpers(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    const int64_t N = n - m + 1;
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active || c->new_len == 0) return;
+    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= s.Npad + 64) return;
+    const int32_t m = c->m;
+    const int64_t N = s.n - m + 1;
+    const double* __restrict__ T = s.T;
     double df = 0.0, dg = 0.0, inv = 0.0;
     if (i < N - 1) {
-        const double a = T[i + m], c = T[i];
-        df = (a - c) * 0.5;
-        dg = (a - mu[i + 1]) + (c - mu[i]);
+        const double a = T[i + m], e = T[i];
+        df = (a - e) * 0.5;
+        dg = (a - s.mu[i + 1]) + (e - s.mu[i]);
     }
     if (i < N) {
-        const double sg = sqrt(var[i]);
-        if (sg <= ctrl->flat_eps) {
-            atomicMin((long long*)&ctrl->flat_min, (long long)i);
-            atomicMax((long long*)&ctrl->flat_max, (long long)i);
+        const double sg = sqrt(s.var[i]);
+        if (sg <= c->flat_eps) {
+            atomicMin((long long*)&c->flat_min, (long long)i);
+            atomicMax((long long*)&c->flat_max, (long long)i);
         } else {
             inv = 1.0 / (sqrt((double)m) * sg);
         }
     }
-    df64[i] = df;
-    dg64[i] = dg;
-    inv64[i] = inv;
-    df32[i] = (float)df;
-    dg32[i] = (float)dg;
-    inv32[i] = (float)inv;
-}
-
-hipError_t launch_stats(const Layout& lay, const Buffers& b, int32_t m, bool init, hipStream_t st)
-{
-    const int64_t len = lay.Npad + 64;
-    const int blocks = (int)((len + 255) / 256);
-    if (init)
-        hipLaunchKernelGGL(k_stats_init, dim3(blocks), dim3(256), 0, st, b.T, lay.n, m, len, b.mu,
-                           b.var, b.ctrl);
-    else
-        hipLaunchKernelGGL(k_stats_update, dim3(blocks), dim3(256), 0, st, b.T, lay.n, m - 1, len,
-                           b.mu, b.var, b.ctrl);
-    hipLaunchKernelGGL(k_helpers, dim3(blocks), dim3(256), 0, st, b.T, lay.n, m, len, b.mu, b.var,
-                       b.df32, b.dg32, b.inv32, b.df64, b.dg64, b.inv64, b.ctrl);
-    return hipGetLastError();
+    s.df64[i] = df;
+    s.dg64[i] = dg;
+    s.inv64[i] = inv;
+    s.df32[i] = (float)df;
+    s.dg32[i] = (float)dg;
+    s.inv32[i] = (float)inv;
 }
 
 // ---------------------------------------------------------------------------
 // round control (MERLIN's r, Alg. 1) and per-round reset
 // ---------------------------------------------------------------------------
-__global__ void k_round_begin(Ctrl* c, const double* hist, int32_t m, int32_t li, int32_t minL,
-                              int attempt, float guard, int64_t N, int64_t Npad,
-                              unsigned long long* alive, unsigned long long* rho, int64_t nwords)
+__global__ void k_round_begin(SeriesDev* S, int B, const int64_t* __restrict__ pfx, float guard)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
+    const int64_t g = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int32_t m = c->m;
     if (g == 0) {
-        if (attempt == 0) {
+        const int li = c->li;
+        if (c->attempt == 0) {
             c->done = 0;
             if (c->mode != 3) {
                 if (li == 0) {
                     c->mode = 0;
-                    c->r = 2.0 * sqrt((double)minL);
+                    c->r = 2.0 * sqrt((double)s.minL);
                 } else if (li <= 4) {
                     c->mode = 1;
-                    c->r = 0.99 * hist[li - 1];
+                    c->r = 0.99 * s.hist[li - 1];
                 } else {
                     double mean = 0.0;
-                    for (int q = 1; q <= 5; ++q) mean += hist[li - q];
+                    for (int q = 1; q <= 5; ++q) mean += s.hist[li - q];
                     mean /= 5.0;
                     double v = 0.0;
                     for (int q = 1; q <= 5; ++q) {
-                        const double d = hist[li - q] - mean;
+                        const double d = s.hist[li - q] - mean;
                         v += d * d;
                     }
                     c->step = sqrt(v / 5.0);
@@ -286,28 +332,26 @@ __global__ void k_round_begin(Ctrl* c, const double* hist, int32_t m, int32_t li
             }
         }
         const double r = c->r;
-        c->m = m;
-        c->li = li;
         c->prune = r > 0.0 ? 1 : 0;
         c->thr64 = r > 0.0 ? 1.0 - r * r / (2.0 * (double)m) : 2.0;
         c->thr_sel = c->thr64 + (double)guard;
         // round up: an FP32 threshold must never prune more than thr_sel
         c->thr32 = __double2float_ru(c->thr_sel);
-        c->nlive_sel = c->maxc_sel = c->ctr_sel = 0;
-        c->nlive_ref = c->maxc_ref = c->ctr_ref = 0;
+        c->nlive_sel = c->maxc_sel = 0;
+        c->nlive_ref = c->maxc_ref = 0;
+        c->ctr_sel = c->ctr_ref = 0ull;
         c->nsurv = 0;
         c->ncand = 0;
     }
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w = g; w < nwords; w += stride) {
-        const int64_t lo = w * 64;
+    const int64_t N = s.n - m + 1;
+    if (g < s.nwords) {
+        const int64_t lo = g * 64;
         unsigned long long bits = 0ull;
         if (lo + 64 <= N) bits = ~0ull;
         else if (lo < N) bits = (1ull << (N - lo)) - 1ull;
-        alive[w] = bits;
+        s.alive[g] = bits;
     }
-    const unsigned long long neg = 0x000fffffffffffffull;  // ordered bits of -inf
-    for (int64_t i = g; i < Npad; i += stride) rho[i] = neg;
+    if (g < s.Npad) s.rho[g] = 0x000fffffffffffffull;  // ordered bits of -inf
 }
 
 // ---------------------------------------------------------------------------
@@ -662,90 +706,39 @@ __device__ __forceinline__ float sel_threshold<float>(const Ctrl* c) { return c-
 template <>
 __device__ __forceinline__ double sel_threshold<double>(const Ctrl* c) { return c->thr_sel; }
 
-// First selection pass: every row tile's nearest near_cols columns, split
-// into chunks of `chunk` columns that run concurrently (blockIdx.y); each
-// stops as soon as the whole tile is dead.
-template <typename F, int Q>
-__global__ __launch_bounds__(64) void k_select_near(SweepArgs<F> A, int near_cols, int chunk)
+template <typename F>
+__device__ __forceinline__ SweepArgs<F> args_of(const SeriesDev& s, Ctrl* c);
+template <>
+__device__ __forceinline__ SweepArgs<float> args_of<float>(const SeriesDev& s, Ctrl* c)
 {
-    extern __shared__ double lds[];
-    const Ctrl* c = A.ctrl;
-    if (!c->prune) return;
-    constexpr int R = 64 * Q;
-    const int64_t i0 = (int64_t)blockIdx.x * R;
-    if (i0 >= A.N) return;
-    const int64_t j00 = i0 + A.m;
-    const int64_t jbeg = j00 + (int64_t)blockIdx.y * chunk;
-    if (jbeg >= A.N || jbeg >= j00 + near_cols) return;
-    const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
-    const F thr = sel_threshold<F>(c);
-    unsigned long long ev = 0;
-    sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
-    if (threadIdx.x == 0 && ev) {
-        atomicAdd(&A.ctrl->evals_sel, ev);
-        atomicAdd(&A.ctrl->evals_near, ev);
-    }
+    SweepArgs<float> A;
+    A.T = s.T;
+    A.mu = s.mu;
+    A.df = s.df32;
+    A.dg = s.dg32;
+    A.inv = s.inv32;
+    A.alive = s.alive;
+    A.rho = s.rho;
+    A.ctrl = c;
+    A.m = c->m;
+    A.N = s.n - A.m + 1;
+    return A;
 }
-
-template <typename F, int Q>
-__global__ __launch_bounds__(64) void k_select_far(SweepArgs<F> A, const int32_t* __restrict__ tiles,
-                                                   int near_cols, int chunk)
+template <>
+__device__ __forceinline__ SweepArgs<double> args_of<double>(const SeriesDev& s, Ctrl* c)
 {
-    extern __shared__ double lds[];
-    Ctrl* c = A.ctrl;
-    if (!c->prune) return;
-    constexpr int R = 64 * Q;
-    const unsigned int nlive = c->nlive_sel;
-    const unsigned long long total = (unsigned long long)nlive * c->maxc_sel;
-    const F thr = sel_threshold<F>(c);
-    unsigned long long ev = 0;
-    for (;;) {
-        unsigned int it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(&c->ctr_sel, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if ((unsigned long long)it >= total) break;
-        const unsigned int cc = it / nlive, p = it % nlive;
-        const int64_t i0 = (int64_t)tiles[p] * R;
-        const int64_t jbeg = i0 + A.m + near_cols + (int64_t)cc * chunk;
-        if (jbeg >= A.N) continue;
-        const int64_t jend = std::min<int64_t>(A.N, jbeg + chunk);
-        sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
-    }
-    if (threadIdx.x == 0 && ev) {
-        atomicAdd(&c->evals_sel, ev);
-        atomicAdd(&c->evals_far, ev);
-    }
-}
-
-// Live-tile lists.  mode 0: selection tiles (R rows), chunks to the right
-// beyond the first pass; mode 1: refinement tiles, chunks on both sides.
-__global__ void k_tiles(const unsigned long long* __restrict__ alive, int64_t N, int32_t m, int R,
-                        int mode, int near_cols, int chunk, int32_t* list, Ctrl* c)
-{
-    if (mode == 0 && !c->prune) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntiles = (N + R - 1) / R;
-    if (t >= ntiles) return;
-    const int words = R / 64;
-    unsigned long long any = 0ull;
-    for (int w = 0; w < words; ++w) any |= alive[t * words + w];
-    if (!any) return;
-    const int64_t i0 = t * R;
-    int64_t nch;
-    if (mode == 0) {
-        const int64_t j0 = i0 + m + near_cols;
-        nch = j0 >= N ? 0 : (N - j0 + chunk - 1) / chunk;
-    } else {
-        const int64_t lend = std::min<int64_t>(N, i0 + R - m);
-        const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
-        const int64_t jr = i0 + m;
-        const int64_t nr = jr < N ? (N - jr + chunk - 1) / chunk : 0;
-        nch = nl + nr;
-    }
-    if (nch <= 0) return;
-    const unsigned int slot = atomicAdd(mode == 0 ? &c->nlive_sel : &c->nlive_ref, 1u);
-    list[slot] = (int32_t)t;
-    atomicMax(mode == 0 ? &c->maxc_sel : &c->maxc_ref, (unsigned int)nch);
+    SweepArgs<double> A;
+    A.T = s.T;
+    A.mu = s.mu;
+    A.df = s.df64;
+    A.dg = s.dg64;
+    A.inv = s.inv64;
+    A.alive = s.alive;
+    A.rho = s.rho;
+    A.ctrl = c;
+    A.m = c->m;
+    A.N = s.n - A.m + 1;
+    return A;
 }
 
 // ----- refinement sweep (FP64) -----
@@ -897,202 +890,192 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     evals += ev;
 }
 
-template <int Q>
-__global__ __launch_bounds__(64) void k_refine(SweepArgs<double> A, const int32_t* __restrict__ tiles,
-                                               int chunk)
+// First selection pass: every row tile's nearest near_cols columns, split
+// into nsub chunks of `chunk` columns that run concurrently; each stops as
+// soon as the whole tile is dead.
+template <typename F, int Q>
+__global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
+                                                    const int64_t* __restrict__ pfx, int near_cols,
+                                                    int chunk, int nsub)
 {
     extern __shared__ double lds[];
-    Ctrl* c = A.ctrl;
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active || !c->prune) return;
     constexpr int R = 64 * Q;
-    const unsigned int nlive = c->nlive_ref;
-    const unsigned long long total = (unsigned long long)nlive * c->maxc_ref;
-    const double thr = c->thr64;
-    const int prune = c->prune;
+    const int64_t lb = blockIdx.x - pfx[b];
+    const SweepArgs<F> A = args_of<F>(s, c);
+    const int64_t i0 = (lb / nsub) * R;
+    if (i0 >= A.N) return;
+    const int64_t j00 = i0 + A.m;
+    const int64_t jbeg = j00 + (lb % nsub) * chunk;
+    if (jbeg >= A.N || jbeg >= j00 + near_cols) return;
+    const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
+    const F thr = sel_threshold<F>(c);
     unsigned long long ev = 0;
-    for (;;) {
-        unsigned int it = 0;
-        if (threadIdx.x == 0) it = atomicAdd(&c->ctr_ref, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if ((unsigned long long)it >= total) break;
-        const unsigned int cc = it / nlive, p = it % nlive;
-        const int64_t i0 = (int64_t)tiles[p] * R;
-        const int64_t lend = std::min<int64_t>(A.N, i0 + R - A.m);
-        const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
-        const int64_t jr = i0 + A.m;
-        const int64_t nr = jr < A.N ? (A.N - jr + chunk - 1) / chunk : 0;
-        if ((int64_t)cc >= nl + nr) continue;
-        const int64_t mn = std::min(nl, nr);
-        bool left;
-        int64_t q;
-        if ((int64_t)cc < 2 * mn) {
-            left = (cc & 1u) != 0u;
-            q = cc >> 1;
-        } else {
-            q = mn + ((int64_t)cc - 2 * mn);
-            left = nl > nr;
-        }
-        int64_t jbeg, jend;
-        if (left) {
-            jend = lend - q * chunk;
-            jbeg = std::max<int64_t>(0, jend - chunk);
-        } else {
-            jbeg = jr + q * chunk;
-            jend = std::min<int64_t>(A.N, jbeg + chunk);
-        }
-        if (jbeg >= jend) continue;
-        ref_item<Q>(A, i0, jbeg, jend, left, thr, prune, lds, ev);
+    sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
+    if (threadIdx.x == 0 && ev) {
+        atomicAdd(&c->evals_sel, ev);
+        atomicAdd(&c->evals_near, ev);
     }
-    if (threadIdx.x == 0 && ev) atomicAdd(&c->evals_ref, ev);
 }
 
+// Remaining selection work: items (live tile, chunk) drawn nearest-first
+// from each series' counter; a workgroup drains the series in rotated order.
+template <typename F, int Q>
+__global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B, int near_cols, int chunk)
+{
+    extern __shared__ double lds[];
+    constexpr int R = 64 * Q;
+    for (int t = 0; t < B; ++t) {
+        const int b = (int)((blockIdx.x + (unsigned int)t) % (unsigned int)B);
+        const SeriesDev& s = S[b];
+        Ctrl* c = s.ctrl;
+        if (!c->active || !c->prune) continue;
+        const unsigned int nlive = c->nlive_sel;
+        const unsigned long long total = (unsigned long long)nlive * c->maxc_sel;
+        if (total == 0) continue;
+        const SweepArgs<F> A = args_of<F>(s, c);
+        const F thr = sel_threshold<F>(c);
+        const int32_t* __restrict__ tiles = s.tsel;
+        unsigned long long ev = 0;
+        for (;;) {
+            unsigned long long it = 0;
+            if (threadIdx.x == 0) it = atomicAdd(&c->ctr_sel, 1ull);
+            it = uniform64(it);
+            if (it >= total) break;
+            const unsigned long long cc = it / nlive;
+            const unsigned int p = (unsigned int)(it % nlive);
+            const int64_t i0 = (int64_t)tiles[p] * R;
+            const int64_t jbeg = i0 + A.m + near_cols + (int64_t)cc * chunk;
+            if (jbeg >= A.N) continue;
+            const int64_t jend = std::min<int64_t>(A.N, jbeg + chunk);
+            sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
+        }
+        if (threadIdx.x == 0 && ev) {
+            atomicAdd(&c->evals_sel, ev);
+            atomicAdd(&c->evals_far, ev);
+        }
+    }
+}
+
+// Live-tile lists.  mode 0: selection tiles (R rows), chunks to the right
+// beyond the first pass; mode 1: refinement tiles, chunks on both sides.
+__global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, int R, int mode,
+                        int near_cols, int chunk)
+{
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
+    if (mode == 0 && !c->prune) return;
+    const int64_t t = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int32_t m = c->m;
+    const int64_t N = s.n - m + 1;
+    const int64_t ntiles = (N + R - 1) / R;
+    if (t >= ntiles) return;
+    const int words = R / 64;
+    unsigned long long any = 0ull;
+    for (int w = 0; w < words; ++w) any |= s.alive[t * words + w];
+    if (!any) return;
+    const int64_t i0 = t * R;
+    int64_t nch;
+    if (mode == 0) {
+        const int64_t j0 = i0 + m + near_cols;
+        nch = j0 >= N ? 0 : (N - j0 + chunk - 1) / chunk;
+    } else {
+        const int64_t lend = std::min<int64_t>(N, i0 + R - m);
+        const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
+        const int64_t jr = i0 + m;
+        const int64_t nr = jr < N ? (N - jr + chunk - 1) / chunk : 0;
+        nch = nl + nr;
+    }
+    if (nch <= 0) return;
+    const unsigned int slot = atomicAdd(mode == 0 ? &c->nlive_sel : &c->nlive_ref, 1u);
+    (mode == 0 ? s.tsel : s.tref)[slot] = (int32_t)t;
+    atomicMax(mode == 0 ? &c->maxc_sel : &c->maxc_ref, (unsigned int)nch);
+}
+
+// Refinement: exact FP64 row maximum of rho over both sides for every tile
+// holding survivors; items drawn nearest-first, alternating right and left.
+template <int Q>
+__global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B, int chunk)
+{
+    extern __shared__ double lds[];
+    constexpr int R = 64 * Q;
+    for (int t = 0; t < B; ++t) {
+        const int b = (int)((blockIdx.x + (unsigned int)t) % (unsigned int)B);
+        const SeriesDev& s = S[b];
+        Ctrl* c = s.ctrl;
+        if (!c->active) continue;
+        const unsigned int nlive = c->nlive_ref;
+        const unsigned long long total = (unsigned long long)nlive * c->maxc_ref;
+        if (total == 0) continue;
+        const SweepArgs<double> A = args_of<double>(s, c);
+        const double thr = c->thr64;
+        const int prune = c->prune;
+        const int32_t* __restrict__ tiles = s.tref;
+        unsigned long long ev = 0;
+        for (;;) {
+            unsigned long long it = 0;
+            if (threadIdx.x == 0) it = atomicAdd(&c->ctr_ref, 1ull);
+            it = uniform64(it);
+            if (it >= total) break;
+            const unsigned long long cc = it / nlive;
+            const unsigned int p = (unsigned int)(it % nlive);
+            const int64_t i0 = (int64_t)tiles[p] * R;
+            const int64_t lend = std::min<int64_t>(A.N, i0 + R - A.m);
+            const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
+            const int64_t jr = i0 + A.m;
+            const int64_t nr = jr < A.N ? (A.N - jr + chunk - 1) / chunk : 0;
+            if ((int64_t)cc >= nl + nr) continue;
+            const int64_t mn = std::min(nl, nr);
+            bool left;
+            int64_t q;
+            if ((int64_t)cc < 2 * mn) {
+                left = (cc & 1u) != 0u;
+                q = cc >> 1;
+            } else {
+                q = mn + ((int64_t)cc - 2 * mn);
+                left = nl > nr;
+            }
+            int64_t jbeg, jend;
+            if (left) {
+                jend = lend - q * chunk;
+                jbeg = std::max<int64_t>(0, jend - chunk);
+            } else {
+                jbeg = jr + q * chunk;
+                jend = std::min<int64_t>(A.N, jbeg + chunk);
+            }
+            if (jbeg >= jend) continue;
+            ref_item<Q>(A, i0, jbeg, jend, left, thr, prune, lds, ev);
+        }
+        if (threadIdx.x == 0 && ev) atomicAdd(&c->evals_ref, ev);
+    }
+}
 
 // Survivor list: every row whose bit is still set.
-__global__ void k_survivors(const unsigned long long* __restrict__ alive, int64_t nwords,
-                            int32_t* surv, Ctrl* c)
+__global__ void k_survivors(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
 {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= nwords) return;
-    unsigned long long bits = alive[w];
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
+    const int64_t w = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t N = s.n - c->m + 1;
+    if (w >= (N + 63) / 64) return;
+    unsigned long long bits = s.alive[w];
     const int cnt = __popcll(bits);
     if (!cnt) return;
     unsigned int base = atomicAdd(&c->nsurv, (unsigned int)cnt);
     while (bits) {
         const int t = __ffsll((long long)bits) - 1;
-        surv[base++] = (int32_t)(w * 64 + t);
+        s.surv[base++] = (int32_t)(w * 64 + t);
         bits &= bits - 1ull;
     }
 }
 
-template <typename F>
-static SweepArgs<F> sweep_args(const Layout& lay, const Buffers& b, int32_t m);
-template <>
-SweepArgs<float> sweep_args<float>(const Layout& lay, const Buffers& b, int32_t m)
-{
-    SweepArgs<float> A;
-    A.T = b.T;
-    A.mu = b.mu;
-    A.df = b.df32;
-    A.dg = b.dg32;
-    A.inv = b.inv32;
-    A.alive = b.alive;
-    A.rho = b.rho;
-    A.ctrl = b.ctrl;
-    A.N = lay.n - m + 1;
-    A.m = m;
-    return A;
-}
-template <>
-SweepArgs<double> sweep_args<double>(const Layout& lay, const Buffers& b, int32_t m)
-{
-    SweepArgs<double> A;
-    A.T = b.T;
-    A.mu = b.mu;
-    A.df = b.df64;
-    A.dg = b.dg64;
-    A.inv = b.inv64;
-    A.alive = b.alive;
-    A.rho = b.rho;
-    A.ctrl = b.ctrl;
-    A.N = lay.n - m + 1;
-    A.m = m;
-    return A;
-}
-
-template <typename F, int Q>
-static void launch_near(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                        hipStream_t st)
-{
-    constexpr int R = 64 * Q;
-    const SweepArgs<F> A = sweep_args<F>(lay, b, m);
-    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
-    const int ntiles = (int)((A.N + R - 1) / R);
-    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
-    cfg.timer->begin(0, st);
-    hipLaunchKernelGGL((k_select_near<F, Q>), dim3(ntiles, nsub), dim3(64), lds, st, A,
-                       cfg.near_cols, cfg.chunk_cols);
-    cfg.timer->end(0, st);
-}
-
-template <typename F, int Q>
-static void launch_far(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                       hipStream_t st)
-{
-    constexpr int R = 64 * Q;
-    const SweepArgs<F> A = sweep_args<F>(lay, b, m);
-    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
-    const int ntiles = (int)((A.N + R - 1) / R);
-    hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, A.N, m, R, 0,
-                       cfg.near_cols, cfg.chunk_cols, b.tsel, b.ctrl);
-    cfg.timer->begin(1, st);
-    hipLaunchKernelGGL((k_select_far<F, Q>), dim3(cfg.far_grid), dim3(64), lds, st, A, b.tsel,
-                       cfg.near_cols, cfg.chunk_cols);
-    cfg.timer->end(1, st);
-}
-
-template <int Q>
-static void launch_refine(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                          hipStream_t st)
-{
-    constexpr int R = 64 * Q;
-    const SweepArgs<double> A = sweep_args<double>(lay, b, m);
-    const int ntiles = (int)((A.N + R - 1) / R);
-    hipLaunchKernelGGL(k_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, st, b.alive, A.N, m, R, 1,
-                       0, cfg.chunk_cols, b.tref, b.ctrl);
-    const size_t lds = sizeof(double) * sweep_lds_doubles(m);
-    cfg.timer->begin(2, st);
-    hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, A, b.tref,
-                       cfg.chunk_cols);
-    cfg.timer->end(2, st);
-}
-
-// Row tiles of 128, 256 or 512 subsequences (Q = 2, 4, 8 rows per lane).
-template <typename F>
-static void launch_select(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                          hipStream_t st)
-{
-    switch (cfg.q_near) {
-    case 2: launch_near<F, 2>(lay, b, cfg, m, st); break;
-    case 4: launch_near<F, 4>(lay, b, cfg, m, st); break;
-    default: launch_near<F, 8>(lay, b, cfg, m, st); break;
-    }
-    switch (cfg.q_far) {
-    case 2: launch_far<F, 2>(lay, b, cfg, m, st); break;
-    case 4: launch_far<F, 4>(lay, b, cfg, m, st); break;
-    default: launch_far<F, 8>(lay, b, cfg, m, st); break;
-    }
-}
-
-hipError_t launch_round(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                        int attempt, hipStream_t st)
-{
-    const int64_t N = lay.n - m + 1;
-    {
-        const int64_t work = std::max<int64_t>(lay.nwords, lay.Npad);
-        const int blocks = (int)std::min<int64_t>(2048, (work + 255) / 256);
-        hipLaunchKernelGGL(k_round_begin, dim3(blocks), dim3(256), 0, st, b.ctrl, b.hist, m,
-                           m - lay.minL, lay.minL, attempt, cfg.guard, N, lay.Npad, b.alive, b.rho,
-                           lay.nwords);
-    }
-    if (cfg.dist_bits == 64)
-        launch_select<double>(lay, b, cfg, m, st);
-    else
-        launch_select<float>(lay, b, cfg, m, st);
-    switch (cfg.q_ref) {
-    case 4: launch_refine<4>(lay, b, cfg, m, st); break;
-    case 8: launch_refine<8>(lay, b, cfg, m, st); break;
-    default: launch_refine<2>(lay, b, cfg, m, st); break;
-    }
-    {
-        const int64_t nw = (N + 63) / 64;
-        hipLaunchKernelGGL(k_survivors, dim3((int)((nw + 255) / 256)), dim3(256), 0, st, b.alive,
-                           nw, b.surv, b.ctrl);
-    }
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// top-k candidates, exact FP64 polish, MERLIN bookkeeping
-// ---------------------------------------------------------------------------
 struct Key {
     unsigned long long u;  // ordered bits of rho (ascending rho = descending nnDist)
     long long i;
@@ -1102,29 +1085,32 @@ __device__ __forceinline__ bool key_less(const Key& x, const Key& y)
     return x.u < y.u || (x.u == y.u && x.i < y.i);
 }
 
-__global__ __launch_bounds__(TOPK_BLOCK) void k_topk(const int32_t* __restrict__ surv,
-                                                     const unsigned long long* __restrict__ rho,
-                                                     Ctrl* c, int k, int64_t* cand)
+__global__ __launch_bounds__(TOPK_BLOCK) void k_topk(SeriesDev* S)
 {
     __shared__ unsigned long long su[TOPK_BLOCK / 64];
     __shared__ long long si[TOPK_BLOCK / 64];
+    const SeriesDev& s = S[blockIdx.x];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
+    const int k = s.k;
     const unsigned int ns = c->nsurv;
     if (ns < (unsigned int)k) {
         if (threadIdx.x == 0) c->ncand = 0;
         return;
     }
-    const int kp = (int)min<unsigned int>(ns, (unsigned int)(k + KP_EXTRA));
+    const int32_t* __restrict__ surv = s.surv;
+    const unsigned long long* __restrict__ rho = s.rho;
+    const int kp = (int)min(ns, (unsigned int)(k + KP_EXTRA));
     Key last = {0ull, -1};
     bool have_last = false;
     for (int r = 0; r < kp; ++r) {
         Key best = {~0ull, 0x7fffffffffffffffll};
-        for (unsigned int s = threadIdx.x; s < ns; s += TOPK_BLOCK) {
-            const long long i = surv[s];
+        for (unsigned int q = threadIdx.x; q < ns; q += TOPK_BLOCK) {
+            const long long i = surv[q];
             const Key x = {rho[i], i};
             if (have_last && !key_less(last, x)) continue;
             if (key_less(x, best)) best = x;
         }
-        // wave reduce
         for (int o = 32; o >= 1; o >>= 1) {
             Key y;
             y.u = __shfl_xor(best.u, o);
@@ -1145,7 +1131,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_topk(const int32_t* __restrict__
             }
             su[0] = bb.u;
             si[0] = bb.i;
-            cand[r] = bb.i;
+            s.cand[r] = bb.i;
         }
         __syncthreads();
         last.u = su[0];
@@ -1159,25 +1145,32 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_topk(const int32_t* __restrict__
 // Exact FP64 nearest-neighbour correlation of the candidate rows against
 // every column: direct centred dot products (no recurrence), the reference
 // the reported distances and neighbour indices come from.  A block owns 256
-// consecutive columns, stages their windows in LDS once and evaluates every
-// candidate against them; it writes one (max rho, argmax j) partial per
-// candidate.
-__global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restrict__ T,
-                                                         const double* __restrict__ mu,
-                                                         const double* __restrict__ var, int64_t N,
-                                                         int32_t m, const int64_t* __restrict__ cand,
-                                                         Ctrl* c, double* part, int64_t npart)
+// consecutive columns of one series, stages their windows in LDS once and
+// evaluates every candidate against them; it writes one (max rho, argmax j)
+// partial per candidate.
+__global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
+                                                         const int64_t* __restrict__ pfx)
 {
     extern __shared__ double lds[];
-    double* ts = lds;                        // T[j0 .. j0 + 256 + m + 64)
-    double* xs = lds + POLISH_BLOCK + m + 64; // centred candidate window, zero padded
     __shared__ double sh[16];
     __shared__ double red_v[POLISH_BLOCK / 64];
     __shared__ long long red_j[POLISH_BLOCK / 64];
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
     const int ncand = (int)c->ncand;
     if (ncand == 0) return;
+    const int32_t m = c->m;
+    const int64_t N = s.n - m + 1;
+    const double* __restrict__ T = s.T;
+    const double* __restrict__ mu = s.mu;
+    const double* __restrict__ var = s.var;
+    double* ts = lds;                          // T[j0 .. j0 + 256 + m + 64)
+    double* xs = lds + POLISH_BLOCK + m + 64;  // centred candidate window, zero padded
     const int tid = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * POLISH_BLOCK;
+    const int64_t blk = blockIdx.x - pfx[b];
+    const int64_t j0 = blk * POLISH_BLOCK;
     for (int t = tid; t < POLISH_BLOCK + m + 64; t += POLISH_BLOCK) ts[t] = T[j0 + t];
     const int64_t j = j0 + tid;
     const double feps = c->flat_eps;
@@ -1187,7 +1180,7 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restric
     const bool flat_j = colok && sgj <= feps;
     unsigned long long ev = 0;
     for (int cid = 0; cid < ncand; ++cid) {
-        const int64_t i = cand[cid];
+        const int64_t i = s.cand[cid];
         const double mui = mu[i];
         double sx = 0.0;
         __syncthreads();  // previous candidate's xs fully consumed
@@ -1205,9 +1198,9 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restric
         double best = -f_inf<double>();
         long long bj = 0x7fffffffffffffffll;
         if (colok && (j <= i - m || j >= i + m)) {
-            double rho;
+            double rh;
             if (flat_i || flat_j) {
-                rho = (flat_i && flat_j) ? 1.0 : 0.0;
+                rh = (flat_i && flat_j) ? 1.0 : 0.0;
             } else {
                 const double* t = ts + tid;
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -1217,11 +1210,11 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restric
                     a2 = fma(xs[k + 2], t[k + 2], a2);
                     a3 = fma(xs[k + 3], t[k + 3], a3);
                 }
-                const double C = (a0 + a1) + (a2 + a3) - muj * Sx;
-                rho = C / ((double)m * sgi * sgj);
-                rho = fmin(1.0, fmax(-1.0, rho));
+                const double Cv = (a0 + a1) + (a2 + a3) - muj * Sx;
+                rh = Cv / ((double)m * sgi * sgj);
+                rh = fmin(1.0, fmax(-1.0, rh));
             }
-            best = rho;
+            best = rh;
             bj = j;
             ++ev;
         }
@@ -1245,9 +1238,9 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restric
                     best = red_v[q];
                     bj = red_j[q];
                 }
-            const int64_t slot = ((int64_t)cid * npart + blockIdx.x) * 2;
-            part[slot] = best;
-            part[slot + 1] = (double)bj;
+            const int64_t slot = ((int64_t)cid * s.npart + blk) * 2;
+            s.part[slot] = best;
+            s.part[slot + 1] = (double)bj;
         }
     }
     ev = (unsigned long long)wave_sum((double)ev);
@@ -1255,16 +1248,23 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(const double* __restric
 }
 
 // Reduce the polish partials of each candidate to (rho, j) in part's tail.
-__global__ void k_polish_reduce(double* part, int64_t npart, Ctrl* c)
+// grid: (KP_MAX, B).
+__global__ void k_polish_reduce(SeriesDev* S)
 {
     __shared__ double rv[4];
     __shared__ double rj[4];
+    const SeriesDev& s = S[blockIdx.y];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
     const int cid = blockIdx.x;
     if ((unsigned int)cid >= c->ncand) return;
+    const int64_t npart = s.npart;
+    const int32_t m = c->m;
+    const int64_t nblk = (s.n - m + 1 + POLISH_BLOCK - 1) / POLISH_BLOCK;
     double best = -f_inf<double>(), bj = 1e300;
-    for (int64_t p = threadIdx.x; p < npart; p += blockDim.x) {
-        const double v = part[((int64_t)cid * npart + p) * 2];
-        const double jj = part[((int64_t)cid * npart + p) * 2 + 1];
+    for (int64_t p = threadIdx.x; p < nblk; p += blockDim.x) {
+        const double v = s.part[((int64_t)cid * npart + p) * 2];
+        const double jj = s.part[((int64_t)cid * npart + p) * 2 + 1];
         if (v > best || (v == best && jj < bj)) {
             best = v;
             bj = jj;
@@ -1291,31 +1291,36 @@ __global__ void k_polish_reduce(double* part, int64_t npart, Ctrl* c)
                 bj = rj[q];
             }
         const int64_t tail = (int64_t)KP_MAX * npart * 2;
-        part[tail + cid * 2] = best;
-        part[tail + cid * 2 + 1] = bj;
+        s.part[tail + cid * 2] = best;
+        s.part[tail + cid * 2 + 1] = bj;
     }
 }
 
 // Rank the polished candidates, write the length's top-k rows when the round
 // found at least k range discords, and advance MERLIN's r otherwise.
-__global__ void k_round_end(const int64_t* __restrict__ cand, const double* __restrict__ part,
-                            int64_t npart, Ctrl* c, double* hist, int32_t m, int32_t li, int k,
-                            int64_t* idx, int32_t* len, double* nn, int64_t* nnidx, int32_t* count)
+// grid: B blocks of 128 threads.
+__global__ void k_round_end(SeriesDev* S)
 {
     __shared__ double nn_s[KP_MAX];
     __shared__ long long id_s[KP_MAX];
     __shared__ long long jj_s[KP_MAX];
+    const SeriesDev& s = S[blockIdx.x];
+    Ctrl* c = s.ctrl;
+    if (!c->active) return;
+    const int k = s.k;
+    const int32_t m = c->m;
+    const int li = c->li;
     const unsigned int ns = c->nsurv;
     const int kp = (int)c->ncand;
     const bool ok = ns >= (unsigned int)k && kp >= k;
-    const int64_t tail = (int64_t)KP_MAX * npart * 2;
+    const int64_t tail = (int64_t)KP_MAX * s.npart * 2;
     const int t = threadIdx.x;
     if (ok && t < kp) {
-        const double rho = part[tail + t * 2];
+        const double rho = s.part[tail + t * 2];
         const double d2 = 2.0 * (double)m * (1.0 - rho);
         nn_s[t] = sqrt(fmin(4.0 * (double)m, fmax(0.0, d2)));
-        id_s[t] = cand[t];
-        jj_s[t] = (long long)part[tail + t * 2 + 1];
+        id_s[t] = s.cand[t];
+        jj_s[t] = (long long)s.part[tail + t * 2 + 1];
     }
     __syncthreads();
     if (ok && t < kp) {
@@ -1324,11 +1329,13 @@ __global__ void k_round_end(const int64_t* __restrict__ cand, const double* __re
             if (nn_s[q] > nn_s[t] || (nn_s[q] == nn_s[t] && id_s[q] < id_s[t])) ++rank;
         if (rank < k) {
             const int64_t row = (int64_t)li * k + rank;
-            idx[row] = id_s[t];
-            len[row] = m;
-            nn[row] = nn_s[t];
-            nnidx[row] = jj_s[t];
-            if (rank == k - 1) hist[li] = nn_s[t];
+            if (s.idx) {
+                s.idx[row] = id_s[t];
+                s.len[row] = m;
+                s.nn[row] = nn_s[t];
+                s.nnidx[row] = jj_s[t];
+            }
+            if (rank == k - 1) s.hist[li] = nn_s[t];
         }
     }
     __syncthreads();
@@ -1337,7 +1344,7 @@ __global__ void k_round_end(const int64_t* __restrict__ cand, const double* __re
         if (ok) {
             c->done = 1;
             c->survivors += ns;
-            if (count) count[li] = (int32_t)ns;
+            if (s.count) s.count[li] = (int32_t)ns;
         } else {
             c->done = 0;
             if (c->mode == 0) c->r *= 0.5;
@@ -1347,94 +1354,226 @@ __global__ void k_round_end(const int64_t* __restrict__ cand, const double* __re
     }
 }
 
-hipError_t launch_finish_length(const Layout& lay, const Buffers& b, const SweepCfg& cfg, int32_t m,
-                                int64_t* idx, int32_t* len, double* nn, int64_t* nnidx,
-                                int32_t* count, hipStream_t st)
+// Series with work left after this round (one block).
+__global__ void k_remaining(SeriesDev* S, int B, int32_t* out)
 {
-    const int64_t N = lay.n - m + 1;
-    hipLaunchKernelGGL(k_topk, dim3(1), dim3(TOPK_BLOCK), 0, st, b.surv, b.rho, b.ctrl, lay.k,
-                       b.cand);
-    const size_t lds = sizeof(double) * (size_t)(POLISH_BLOCK + 2 * (m + 64));
+    __shared__ int cnt[2];
+    if (threadIdx.x == 0) {
+        cnt[0] = 0;
+        cnt[1] = 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const Ctrl* c = S[b].ctrl;
+        const bool left = !c->finished && !(c->started && c->done && c->m >= S[b].maxL);
+        if (left) atomicAdd(&cnt[0], 1);
+        if (c->error) atomicAdd(&cnt[1], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = cnt[0];
+        out[1] = cnt[1];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename F, int Q>
+static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
+    if (total[PFX_NEAR] == 0) return;
+    cfg.timer->begin(0, st);
+    hipLaunchKernelGGL((k_select_near<F, Q>), dim3((unsigned int)total[PFX_NEAR]), dim3(64), lds,
+                       st, bt.s, bt.B, bt.pfx[PFX_NEAR], cfg.near_cols, cfg.chunk_cols, nsub);
+    cfg.timer->end(0, st);
+}
+
+template <typename F, int Q>
+static void launch_far(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TSEL]), dim3(256), 0, st, bt.s, bt.B,
+                       bt.pfx[PFX_TSEL], 64 * Q, 0, cfg.near_cols, cfg.chunk_cols);
+    cfg.timer->begin(1, st);
+    hipLaunchKernelGGL((k_select_far<F, Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
+                       cfg.near_cols, cfg.chunk_cols);
+    cfg.timer->end(1, st);
+}
+
+template <int Q>
+static void launch_refine(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TREF]), dim3(256), 0, st, bt.s, bt.B,
+                       bt.pfx[PFX_TREF], 64 * Q, 1, 0, cfg.chunk_cols);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    cfg.timer->begin(2, st);
+    hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
+                       cfg.chunk_cols);
+    cfg.timer->end(2, st);
+}
+
+template <typename F>
+static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* total,
+                          hipStream_t st)
+{
+    switch (cfg.q_near) {
+    case 2: launch_near<F, 2>(bt, cfg, total, st); break;
+    case 4: launch_near<F, 4>(bt, cfg, total, st); break;
+    default: launch_near<F, 8>(bt, cfg, total, st); break;
+    }
+    switch (cfg.q_far) {
+    case 2: launch_far<F, 2>(bt, cfg, total, st); break;
+    case 4: launch_far<F, 4>(bt, cfg, total, st); break;
+    default: launch_far<F, 8>(bt, cfg, total, st); break;
+    }
+}
+
+// One round: every series with work does one range search at its current
+// length (a fixed launch sequence; all parameters come from the device).
+hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
+{
+    const unsigned int elem = (unsigned int)total[PFX_ELEM];
+    hipLaunchKernelGGL(k_round_prep, dim3((bt.B + 63) / 64), dim3(64), 0, st, bt.s, bt.B);
+    hipLaunchKernelGGL(k_stats, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
+    hipLaunchKernelGGL(k_helpers, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
+    hipLaunchKernelGGL(k_round_begin, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM],
+                       cfg.guard);
+    if (cfg.dist_bits == 64) launch_select<double>(bt, cfg, total, st);
+    else launch_select<float>(bt, cfg, total, st);
+    switch (cfg.q_ref) {
+    case 4: launch_refine<4>(bt, cfg, total, st); break;
+    case 8: launch_refine<8>(bt, cfg, total, st); break;
+    default: launch_refine<2>(bt, cfg, total, st); break;
+    }
+    hipLaunchKernelGGL(k_survivors, dim3((unsigned int)total[PFX_WORDS]), dim3(256), 0, st, bt.s,
+                       bt.B, bt.pfx[PFX_WORDS]);
+    hipLaunchKernelGGL(k_topk, dim3(bt.B), dim3(TOPK_BLOCK), 0, st, bt.s);
+    const size_t lds = sizeof(double) * (size_t)(POLISH_BLOCK + 2 * (bt.maxL_all + 64));
     cfg.timer->begin(3, st);
-    hipLaunchKernelGGL(k_polish, dim3((unsigned int)lay.npart), dim3(POLISH_BLOCK), lds, st, b.T,
-                       b.mu, b.var, N, m, b.cand, b.ctrl, b.part, lay.npart);
+    hipLaunchKernelGGL(k_polish, dim3((unsigned int)total[PFX_POLISH]), dim3(POLISH_BLOCK), lds, st,
+                       bt.s, bt.B, bt.pfx[PFX_POLISH]);
     cfg.timer->end(3, st);
-    hipLaunchKernelGGL(k_polish_reduce, dim3(lay.kp), dim3(256), 0, st, b.part, lay.npart, b.ctrl);
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(KP_MAX < 64 ? 64 : 128), 0, st, b.cand, b.part,
-                       lay.npart, b.ctrl, b.hist, m, m - lay.minL, lay.k, idx, len, nn, nnidx,
-                       count);
+    hipLaunchKernelGGL(k_polish_reduce, dim3(KP_MAX, bt.B), dim3(256), 0, st, bt.s);
+    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(128), 0, st, bt.s);
+    hipLaunchKernelGGL(k_remaining, dim3(1), dim3(256), 0, st, bt.s, bt.B, bt.remaining);
     return hipGetLastError();
 }
 
-__global__ void k_set_fixed_r(Ctrl* c, double r)
+__global__ void k_set_fixed_r(SeriesDev* S, double r)
 {
+    Ctrl* c = S[0].ctrl;
     c->mode = 3;
     c->r = r;
 }
 
-__global__ void k_set_max_len(Ctrl* c, int32_t maxm) { c->m = maxm; }
-
-hipError_t launch_set_max_len(const Buffers& b, int32_t maxm, hipStream_t st)
+hipError_t launch_set_fixed_r(const Batch& bt, double r, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_set_max_len, dim3(1), dim3(1), 0, st, b.ctrl, maxm);
+    hipLaunchKernelGGL(k_set_fixed_r, dim3(1), dim3(1), 0, st, bt.s, r);
     return hipGetLastError();
 }
 
-hipError_t launch_set_fixed_r(const Buffers& b, double r, hipStream_t st)
+__global__ void k_set_len(SeriesDev* S, int32_t m, int32_t new_len)
 {
-    hipLaunchKernelGGL(k_set_fixed_r, dim3(1), dim3(1), 0, st, b.ctrl, r);
+    Ctrl* c = S[0].ctrl;
+    c->m = m;
+    c->new_len = new_len;
+    c->active = 1;
+}
+
+hipError_t launch_set_len(const Batch& bt, int32_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, m, 0);
     return hipGetLastError();
 }
 
-__global__ void k_range_out(const unsigned long long* __restrict__ alive,
-                            const unsigned long long* __restrict__ rho, int64_t N, int32_t m,
-                            unsigned long long* alive_out, double* nn_out)
+// Statistics of S[0] at lengths minL..m only (no search).
+hipError_t launch_stats_to(const Batch& bt, int32_t minL, int32_t m, const int64_t* total,
+                           hipStream_t st)
 {
+    for (int32_t mm = minL; mm <= m; ++mm) {
+        hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, mm, mm == minL ? 2 : 1);
+        hipLaunchKernelGGL(k_stats, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
+                           bt.pfx[PFX_ELEM]);
+    }
+    return hipGetLastError();
+}
+
+// Sum of the per-series counters of a call (one block):
+// out = {evals_sel, evals_ref, evals_pol, rounds, survivors, evals_near, evals_far}.
+__global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
+{
+    __shared__ unsigned long long acc[7];
+    if (threadIdx.x < 7) acc[threadIdx.x] = 0ull;
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const Ctrl* c = S[b].ctrl;
+        atomicAdd(&acc[0], c->evals_sel);
+        atomicAdd(&acc[1], c->evals_ref);
+        atomicAdd(&acc[2], c->evals_pol);
+        atomicAdd(&acc[3], c->rounds);
+        atomicAdd(&acc[4], c->survivors);
+        atomicAdd(&acc[5], c->evals_near);
+        atomicAdd(&acc[6], c->evals_far);
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) out[threadIdx.x] = acc[threadIdx.x];
+}
+
+hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_stats, dim3(1), dim3(256), 0, st, bt.s, bt.B, out);
+    return hipGetLastError();
+}
+
+__global__ void k_range_out(SeriesDev* S, int64_t N, unsigned long long* alive_out, double* nn_out)
+{
+    const SeriesDev& s = S[0];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const bool on = (alive[i >> 6] >> (i & 63)) & 1ull;
-    if ((i & 63) == 0) alive_out[i >> 6] = alive[i >> 6];
+    const int32_t m = s.ctrl->m;
+    const bool on = (s.alive[i >> 6] >> (i & 63)) & 1ull;
+    if ((i & 63) == 0) alive_out[i >> 6] = s.alive[i >> 6];
     double d = 0.0;
     if (on) {
-        const double r = dbl_of(rho[i]);
+        const double r = dbl_of(s.rho[i]);
         d = sqrt(fmin(4.0 * (double)m, fmax(0.0, 2.0 * (double)m * (1.0 - r))));
     }
     nn_out[i] = d;
 }
 
-hipError_t launch_range_out(const Layout& lay, const Buffers& b, int32_t m,
-                            unsigned long long* alive_out, double* nn_out, hipStream_t st)
+hipError_t launch_range_out(const Batch& bt, int64_t N, unsigned long long* alive_out,
+                            double* nn_out, hipStream_t st)
 {
-    const int64_t N = lay.n - m + 1;
-    hipLaunchKernelGGL(k_range_out, dim3((int)((N + 255) / 256)), dim3(256), 0, st, b.alive, b.rho,
-                       N, m, alive_out, nn_out);
+    hipLaunchKernelGGL(k_range_out, dim3((unsigned int)((N + 255) / 256)), dim3(256), 0, st, bt.s,
+                       N, alive_out, nn_out);
     return hipGetLastError();
 }
 
-__global__ void k_stats_out(const double* __restrict__ mu, const double* __restrict__ var, int64_t N,
-                            double* mo, double* so)
+__global__ void k_stats_out(SeriesDev* S, int64_t N, double* mo, double* so)
 {
+    const SeriesDev& s = S[0];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    mo[i] = mu[i];
-    so[i] = sqrt(var[i]);
+    mo[i] = s.mu[i];
+    so[i] = sqrt(s.var[i]);
 }
 
-hipError_t launch_stats_out(const Layout& lay, const Buffers& b, int32_t m, double* mu,
-                            double* sigma, hipStream_t st)
+hipError_t launch_stats_out(const Batch& bt, int64_t N, double* mu, double* sigma, hipStream_t st)
 {
-    const int64_t N = lay.n - m + 1;
-    hipLaunchKernelGGL(k_stats_out, dim3((int)((N + 255) / 256)), dim3(256), 0, st, b.mu, b.var, N,
-                       mu, sigma);
+    hipLaunchKernelGGL(k_stats_out, dim3((unsigned int)((N + 255) / 256)), dim3(256), 0, st, bt.s,
+                       N, mu, sigma);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// workspace layout
+// per-series workspace layout and work geometry
 // ---------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, int32_t dist_bits, Layout* out)
+bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
 {
     Layout l = {};
     l.n = n;
@@ -1443,7 +1582,6 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, int32_t dist_
     l.k = k;
     l.L = maxL - minL + 1;
     l.kp = k + KP_EXTRA;
-    l.dist_bits = dist_bits;
     l.Nmax = n - minL + 1;
     l.Npad = ((l.Nmax + 1 + R_MAX - 1) / R_MAX) * R_MAX + R_MAX;
     l.Tlen = l.Npad + maxL + 256;
@@ -1463,8 +1601,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, int32_t dist_
     l.off_surv = o;  o = al256(o + sizeof(int32_t) * (size_t)l.Npad);
     l.off_cand = o;  o = al256(o + sizeof(int64_t) * (size_t)KP_MAX);
     l.off_part = o;  o = al256(o + sizeof(double) * (size_t)(2 * KP_MAX * (l.npart + 1)));
-    l.off_hist = o;  o = al256(o + sizeof(double) * (size_t)l.L);
-    l.off_flat = o;  o = al256(o + sizeof(int64_t) * 2);
+    l.off_hist = o;  o = al256(o + sizeof(double) * (size_t)(l.L > 0 ? l.L : 1));
     l.off_ctrl = o;  o = al256(o + sizeof(Ctrl));
     l.off_red = o;   o = al256(o + sizeof(double) * 2 * RED_BLOCKS);
     l.total = o;
@@ -1472,32 +1609,54 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, int32_t dist_
     return true;
 }
 
-Buffers carve(void* ws, const Layout& l)
+SeriesDev carve(void* base, const Layout& l)
 {
-    char* p = (char*)ws;
+    char* p = (char*)base;
     const size_t hl = (size_t)(l.Npad + 64);
-    Buffers b;
-    b.T = (double*)(p + l.off_T);
-    b.mu = (double*)(p + l.off_mu);
-    b.var = (double*)(p + l.off_var);
-    b.df32 = (float*)(p + l.off_h32);
-    b.dg32 = (float*)(p + l.off_h32 + al256(sizeof(float) * hl));
-    b.inv32 = (float*)(p + l.off_h32 + 2 * al256(sizeof(float) * hl));
-    b.df64 = (double*)(p + l.off_h64);
-    b.dg64 = (double*)(p + l.off_h64 + al256(sizeof(double) * hl));
-    b.inv64 = (double*)(p + l.off_h64 + 2 * al256(sizeof(double) * hl));
-    b.alive = (unsigned long long*)(p + l.off_alive);
-    b.rho = (unsigned long long*)(p + l.off_rho);
-    b.tsel = (int32_t*)(p + l.off_tsel);
-    b.tref = (int32_t*)(p + l.off_tref);
-    b.surv = (int32_t*)(p + l.off_surv);
-    b.cand = (int64_t*)(p + l.off_cand);
-    b.part = (double*)(p + l.off_part);
-    b.hist = (double*)(p + l.off_hist);
-    b.flat = (int64_t*)(p + l.off_flat);
-    b.ctrl = (Ctrl*)(p + l.off_ctrl);
-    b.red = (double*)(p + l.off_red);
-    return b;
+    SeriesDev s = {};
+    s.n = l.n;
+    s.Nmax = l.Nmax;
+    s.Npad = l.Npad;
+    s.Tlen = l.Tlen;
+    s.nwords = l.nwords;
+    s.npart = l.npart;
+    s.minL = l.minL;
+    s.maxL = l.maxL;
+    s.k = l.k;
+    s.kp = l.kp;
+    s.L = l.L;
+    s.T = (double*)(p + l.off_T);
+    s.mu = (double*)(p + l.off_mu);
+    s.var = (double*)(p + l.off_var);
+    s.df32 = (float*)(p + l.off_h32);
+    s.dg32 = (float*)(p + l.off_h32 + al256(sizeof(float) * hl));
+    s.inv32 = (float*)(p + l.off_h32 + 2 * al256(sizeof(float) * hl));
+    s.df64 = (double*)(p + l.off_h64);
+    s.dg64 = (double*)(p + l.off_h64 + al256(sizeof(double) * hl));
+    s.inv64 = (double*)(p + l.off_h64 + 2 * al256(sizeof(double) * hl));
+    s.alive = (unsigned long long*)(p + l.off_alive);
+    s.rho = (unsigned long long*)(p + l.off_rho);
+    s.tsel = (int32_t*)(p + l.off_tsel);
+    s.tref = (int32_t*)(p + l.off_tref);
+    s.surv = (int32_t*)(p + l.off_surv);
+    s.cand = (int64_t*)(p + l.off_cand);
+    s.part = (double*)(p + l.off_part);
+    s.hist = (double*)(p + l.off_hist);
+    s.ctrl = (Ctrl*)(p + l.off_ctrl);
+    s.red = (double*)(p + l.off_red);
+    return s;
+}
+
+void series_blocks(const Layout& l, const SweepCfg& cfg, int64_t out[PFX_KINDS])
+{
+    const int rn = 64 * cfg.q_near, rf = 64 * cfg.q_far, rr = 64 * cfg.q_ref;
+    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
+    out[PFX_ELEM] = (l.Npad + 64 + 255) / 256;
+    out[PFX_NEAR] = ((l.Nmax + rn - 1) / rn) * nsub;
+    out[PFX_TSEL] = ((l.Nmax + rf - 1) / rf + 255) / 256;
+    out[PFX_TREF] = ((l.Nmax + rr - 1) / rr + 255) / 256;
+    out[PFX_WORDS] = (l.nwords + 255) / 256;
+    out[PFX_POLISH] = l.npart;
 }
 
 }  // namespace palmad

@@ -83,3 +83,54 @@ def test_null_pointer_arguments_are_rejected():
     assert L.palmad_discords(None, None, 1000, 10, 20, 1, None, None, 0, None, None, None,
                              None, None, None, None) == -1
     L.palmad_destroy(None)
+
+
+def _bws(lengths, lo, hi, k, **kw):
+    B = len(lengths)
+    offs = (ctypes.c_int64 * (B + 1))()
+    for b, n in enumerate(lengths):
+        offs[b + 1] = offs[b] + n
+    c_lo = (ctypes.c_int32 * max(B, 1))(*lo)
+    c_hi = (ctypes.c_int32 * max(B, 1))(*hi)
+    o = _lib.make_options(**kw)
+    b = ctypes.c_size_t(0)
+    rc = _lib.lib().palmad_batched_workspace_size(B, offs, c_lo, c_hi, k, ctypes.byref(o),
+                                                  ctypes.byref(b))
+    return rc, b.value
+
+
+def test_batched_workspace_size():
+    rc, one = _ws(20000, 50, 100, 1)
+    assert rc == 0
+    rc, b1 = _bws([20000], [50], [100], 1)
+    assert rc == 0 and b1 >= one
+    rc, b3 = _bws([20000, 5000, 70000], [50, 10, 60], [100, 30, 110], 1)
+    assert rc == 0 and b3 > b1
+    # the per-series regions dominate: the batch needs about the sum
+    parts = [_ws(n, lo, hi, 1)[1] for n, lo, hi in ((20000, 50, 100), (5000, 10, 30),
+                                                     (70000, 60, 110))]
+    assert abs(b3 - sum(parts)) <= 64 * 1024
+
+
+@pytest.mark.parametrize("lengths,lo,hi,k,code", [
+    ([], [], [], 1, -1),                         # B = 0
+    ([1000, 50], [10, 10], [20, 20], 1, -1),     # second series too short for maxL
+    ([1000, 1000], [10, 2], [20, 20], 1, -1),    # minL < 3
+    ([1000, 1000], [10, 10], [20, 20], 65, -6),  # k above the supported maximum
+])
+def test_batched_workspace_size_rejects_bad_arguments(lengths, lo, hi, k, code):
+    rc, _ = _bws(lengths, lo, hi, k)
+    assert rc == code
+    msg = _lib.lib().palmad_last_error(None).decode()
+    assert msg
+    if len(lengths) == 2 and code == -1:
+        assert "series 1" in msg
+
+
+def test_batched_offsets_must_start_at_zero():
+    offs = (ctypes.c_int64 * 2)(5, 2005)
+    lo = (ctypes.c_int32 * 1)(10)
+    hi = (ctypes.c_int32 * 1)(20)
+    b = ctypes.c_size_t(0)
+    assert _lib.lib().palmad_batched_workspace_size(1, offs, lo, hi, 1, None, ctypes.byref(b)) == -1
+    assert _lib.lib().palmad_batched_workspace_size(1, None, lo, hi, 1, None, ctypes.byref(b)) == -1

@@ -1,0 +1,153 @@
+"""Batched search: many series of uneven length, each with its own length
+range, in one call (one round of launches serves every series).
+
+Every series runs the same per-series arithmetic as the single-series entry
+point, so the batched results must be identical to it bit for bit; the
+single-series path is itself checked against the oracle, and the small
+cases here are checked against brute force as well.  The full 64-series
+workload is checked against the single-series path for every series and
+against the oracle's exact nearest-neighbour distance on sampled rows.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_01660_amd import synth
+from parity_helpers import check_against_profiles
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+KEYS = ("idx", "len", "nn_dist", "nn_idx", "count")
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _small_batch():
+    rng = np.random.default_rng(4242)
+    out = []
+    for b in range(7):
+        kind = ("rw", "noise", "ecg")[b % 3]
+        maxL = int(rng.integers(8, 60))
+        minL = max(3, maxL - int(rng.integers(0, 6)))
+        n = int(rng.integers(3 * maxL, 3500))
+        out.append((synth.small_random(900 + b, n, kind), minL, maxL))
+    return out
+
+
+@pytest.mark.parametrize("dist_bits", [64, 32])
+def test_batched_equals_single_and_bruteforce(dist_bits):
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    cases = _small_batch()
+    k = 2
+    _say("batched small", dist_bits, [(T.shape[0], lo, hi) for T, lo, hi in cases])
+    res = api.discords_batched([torch.from_numpy(T).to(dev) for T, _, _ in cases],
+                               [lo for _, lo, _ in cases], [hi for _, _, hi in cases], k,
+                               dist_bits=dist_bits)
+    for b, (T, lo, hi) in enumerate(cases):
+        _say("batched small series", b)
+        one = api.discords(torch.from_numpy(T).to(dev), lo, hi, k, dist_bits=dist_bits)
+        for key in KEYS:
+            assert torch.equal(res[b][key], one[key]), (b, key)
+        check_against_profiles(T, res[b], lo, hi, k)
+
+
+def test_batched_graph_replay_and_direct_launch_agree():
+    """The cached round graph (reused across calls on one workspace) and
+    direct launches give the same result."""
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    cases = _small_batch()
+    values = [torch.from_numpy(T).to(dev) for T, _, _ in cases]
+    lo = [c[1] for c in cases]
+    hi = [c[2] for c in cases]
+    nbytes = api.batched_workspace_size([v.shape[0] for v in values], lo, hi, 3)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _say("batched graph replay")
+    a = api.discords_batched(values, lo, hi, 3, workspace=ws)
+    b = api.discords_batched(values, lo, hi, 3, workspace=ws)
+    c = api.discords_batched(values, lo, hi, 3, workspace=ws, graphs=False)
+    d, st = api.discords_batched(values, lo, hi, 3, workspace=ws, time_kernels=True,
+                                 return_stats=True)
+    for s in range(len(cases)):
+        for key in KEYS:
+            assert torch.equal(a[s][key], b[s][key]), (s, key)
+            assert torch.equal(a[s][key], c[s][key]), (s, key)
+            assert torch.equal(a[s][key], d[s][key]), (s, key)
+    assert st["range_searches"] >= sum(h - l + 1 for l, h in zip(lo, hi))
+    assert st["kernel_launches"][0] > 0
+
+
+def test_batched_single_series_equals_plain():
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    T = torch.from_numpy(synth.small_random(31, 5000, "ecg")).to(dev)
+    _say("batched B=1")
+    a = api.discords_batched([T], 20, 26, 4)[0]
+    b = api.discords(T, 20, 26, 4)
+    for key in KEYS:
+        assert torch.equal(a[key], b[key]), key
+
+
+def test_batched_nonfinite_names_the_series():
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    from paper_2304_01660_amd._lib import PalmadError
+    cases = _small_batch()
+    bad = cases[3][0].copy()
+    bad[17] = np.inf
+    vals = [torch.from_numpy(T).to(dev) for T, _, _ in cases]
+    vals[3] = torch.from_numpy(bad).to(dev)
+    _say("batched nonfinite")
+    with pytest.raises(PalmadError) as ei:
+        api.discords_batched(vals, [c[1] for c in cases], [c[2] for c in cases], 1)
+    assert ei.value.code == -2
+    assert "series 3" in str(ei.value)
+
+
+def test_config4_batched_full_size():
+    """The 64-series workload: identical to 64 single-series calls; sampled
+    rows match the oracle's exact nearest neighbour; sampled rows never
+    beat the reported top-1."""
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    ws = synth.config4()
+    _say("config4 batched", len(ws))
+    res, st = api.discords_batched([torch.from_numpy(w.T).to(dev) for w in ws],
+                                   [w.minL for w in ws], [w.maxL for w in ws], 1,
+                                   return_stats=True)
+    _say("config4 stats", st)
+    rng = np.random.default_rng(404)
+    for b, w in enumerate(ws):
+        one = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, 1)
+        for key in KEYS:
+            assert torch.equal(res[b][key], one[key]), (b, w.name, key)
+        nn = res[b]["nn_dist"].cpu().numpy()
+        idx = res[b]["idx"].cpu().numpy()
+        nnj = res[b]["nn_idx"].cpu().numpy()
+        L = w.maxL - w.minL + 1
+        assert np.all(res[b]["len"].cpu().numpy() == np.arange(w.minL, w.maxL + 1))
+        assert np.all(nn > 0) and np.all(nn <= 2 * np.sqrt(np.arange(w.minL, w.maxL + 1)) + 1e-12)
+        if b % 8 == 0:
+            q = int(rng.integers(0, L))
+            m = w.minL + q
+            _say("config4 oracle row", b, w.name, m, idx[q])
+            d, j = oracle.nn_row(w.T, m, int(idx[q]))
+            assert abs(d * d - nn[q] * nn[q]) <= 2 * m * 1e-12 + 2e-9 * d * d, (b, q, d, nn[q])
+            assert j == nnj[q]
+            for i in rng.integers(0, w.n - m + 1, size=4):
+                d, _ = oracle.nn_row(w.T, m, int(i))
+                assert d <= nn[q] * (1 + 1e-9), (b, m, i, d, nn[q])

@@ -22,21 +22,14 @@ import pytest
 import oracle
 from oracle import bruteforce as bf
 from paper_2304_01660_amd import synth
+from parity_helpers import REL, close_ed
+from parity_helpers import check_against_profiles as _check_against_profiles
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-REL = 1e-9
-RHO_ABS = 1e-12
-
-
-def close_ed(a, b, m, rel=REL):
-    """|a^2 - b^2| within 2m*RHO_ABS + rel*b^2 (elementwise, numpy)."""
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return np.abs(a * a - b * b) <= 2.0 * m * RHO_ABS + 2.0 * rel * b * b + 1e-300
 
 
 def _dev():
@@ -52,32 +45,6 @@ def _say(*a):
 def _api():
     from paper_2304_01660_amd import api
     return api
-
-
-def _check_against_profiles(T, out, minL, maxL, k, rel=REL):
-    idx = out["idx"].cpu().numpy()
-    ln = out["len"].cpu().numpy()
-    nn = out["nn_dist"].cpu().numpy()
-    nnj = out["nn_idx"].cpu().numpy()
-    cnt = out["count"].cpu().numpy()
-    assert np.all(cnt >= k)
-    for m in range(minL, maxL + 1):
-        P, J = bf.profile(T, m)
-        rows = slice((m - minL) * k, (m - minL + 1) * k)
-        exp = bf.topk(P, k)
-        assert np.all(ln[rows] == m)
-        for q in range(k):
-            g, e = int(idx[rows][q]), int(exp[q])
-            if g != e:
-                assert close_ed(P[g], P[e], m, rel), (m, q, g, e, P[g], P[e])
-            assert close_ed(nn[rows][q], P[g], m, rel), (m, q, nn[rows][q], P[g])
-            j = int(nnj[rows][q])
-            assert abs(j - g) >= m
-            # the reported neighbour realises the nearest distance
-            Zg = (T[g:g + m] - T[g:g + m].mean()) / T[g:g + m].std()
-            Zj = (T[j:j + m] - T[j:j + m].mean()) / T[j:j + m].std()
-            d = math.sqrt(((Zg - Zj) ** 2).sum())
-            assert abs(d - P[g]) <= 1e-7 * max(1.0, P[g]), (m, q, j, J[g], d, P[g])
 
 
 def test_window_stats_match_oracle():
