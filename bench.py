@@ -65,11 +65,13 @@ def cpu_baseline(w, golden, n_lengths: int):
     }
 
 
-def batched_vs_plain(api, synth, torch, dev, reps: int):
+def batched_vs_plain(api, synth, torch, dev, reps: int, tune: bool):
     """64 uneven series (lengths log-uniform in [1e4, 2e5], each with its own
     length range of 51 lengths, top-1): one batched call against a loop of
-    single-series calls over the same series (best of graph replay and direct
-    launches for the loop)."""
+    single-series calls over the same series.  The batched call uses tile
+    geometry from the autotuner (tuned on the batch, outside the timing); the
+    loop gets the best of: default geometry with graph replay, default
+    geometry with direct launches, and the tuned geometry."""
     ws = synth.config4()
     vals = [torch.from_numpy(w.T).to(dev) for w in ws]
     lo = [w.minL for w in ws]
@@ -79,30 +81,36 @@ def batched_vs_plain(api, synth, torch, dev, reps: int):
     wsb = torch.empty(nb, dtype=torch.uint8, device=dev)
     flat = torch.cat(vals)
     sizes = [v.shape[0] for v in vals]
-    res = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb)  # warm-up
+    tuned, report = ({}, None)
+    if tune:
+        tuned, report = api.autotune(vals, lo, hi, 1, probe_lengths=6, reps=1)
+    res = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb, **tuned)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         res, st = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb,
-                                       return_stats=True)
+                                       return_stats=True, **tuned)
     torch.cuda.synchronize()
     t_batched = (time.perf_counter() - t0) / reps
     evals_b = st["evals_select"] + st["evals_refine"] + st["evals_polish"]
     wss = [torch.empty(api.workspace_size(w.n, w.minL, w.maxL, 1), dtype=torch.uint8, device=dev)
            for w in ws]
     plain = {}
-    for graphs in (True, False):
+    variants = {"default_graph": dict(graphs=True), "default_direct": dict(graphs=False)}
+    if tuned:
+        variants["tuned_graph"] = dict(tuned)
+    for name, kw in variants.items():
         for b, w in enumerate(ws):  # warm-up
-            api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], graphs=graphs)
+            api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            outs = [api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], graphs=graphs)
+            outs = [api.discords(vals[b], w.minL, w.maxL, 1, workspace=wss[b], **kw)
                     for b, w in enumerate(ws)]
         torch.cuda.synchronize()
-        plain[graphs] = (time.perf_counter() - t0) / reps
+        plain[name] = (time.perf_counter() - t0) / reps
     same = all(torch.equal(res[b][key], outs[b][key]) for b in range(len(ws))
-               for key in ("idx", "nn_dist", "nn_idx", "count"))
+               for key in ("idx", "len", "nn_dist", "nn_idx", "count"))
     t_plain = min(plain.values())
     return {
         "workload": "batch64_rw+ecg_n1e4-2e5_m(50..100)+50_k1_fp32",
@@ -114,10 +122,11 @@ def batched_vs_plain(api, synth, torch, dev, reps: int):
         "batched_evals_per_s": evals_b / t_batched,
         "plain_loop_s": t_plain,
         "plain_loop_lengths_per_s": lengths / t_plain,
-        "plain_loop_graph_s": plain[True],
-        "plain_loop_direct_s": plain[False],
+        "plain_loop_variants_s": plain,
         "speedup": t_plain / t_batched,
-        "results_identical": bool(same),
+        "results_identical_to_last_loop_variant": bool(same),
+        "tuned_options": tuned,
+        "tune_report": report,
         "reps": reps,
     }
 
@@ -145,6 +154,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-lengths", type=int, default=6)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,15 +173,19 @@ def main():
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     T = torch.from_numpy(w.T).to(dev)
     ws = torch.empty(api.workspace_size(w.n, w.minL, w.maxL, w.k), dtype=torch.uint8, device=dev)
+    # tile geometry from the autotuner (probing the first lengths), untimed
+    tuned, tune_report = ({}, None)
+    if not args.no_tune:
+        tuned, tune_report = api.autotune(T, w.minL, w.maxL, w.k, probe_lengths=8, reps=1)
     for _ in range(args.warmup):
-        api.discords(T, w.minL, w.maxL, w.k, workspace=ws)
+        api.discords(T, w.minL, w.maxL, w.k, workspace=ws, **tuned)
     torch.cuda.synchronize()
 
     # timed region: the production path (round graphs replayed, no events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True)
+        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True, **tuned)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt / args.steps * 1e3
@@ -184,7 +198,7 @@ def main():
     t1 = time.perf_counter()
     for _ in range(args.steps):
         out_t = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True,
-                             time_kernels=True)
+                             time_kernels=True, **tuned)
         st = out_t["stats"]
         if agg is None:
             agg = {k: (list(v) if isinstance(v, list) else v) for k, v in st.items()}
@@ -231,7 +245,9 @@ def main():
         "evals_per_launch": (dk["evals_per_step"] / dk["launches_per_step"]
                              if dk["launches_per_step"] else None),
     }
-    batched = None if args.no_batched else batched_vs_plain(api, synth, torch, dev, args.batch_reps)
+    batched = None
+    if not args.no_batched:
+        batched = batched_vs_plain(api, synth, torch, dev, args.batch_reps, not args.no_tune)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_lengths)
@@ -253,7 +269,9 @@ def main():
             "workload": w.name,
             "n": w.n, "minL": w.minL, "maxL": w.maxL, "k": w.k, "lengths": L,
             "series": "seeded random walk with 5 injected sine bursts/level shifts (seed 1)",
+            "tile_options": tuned or "defaults",
         },
+        "tune_report": tune_report,
         "evals_per_s": evals / dt,
         "range_searches_per_step": st_prod["range_searches"],
         "ms_per_step_instrumented": ms_instrumented,

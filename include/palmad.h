@@ -195,6 +195,47 @@ int palmad_discords_batched(palmad_ctx* ctx, const double* values, const int64_t
                             int64_t* idx, int32_t* len, double* nn_dist, int64_t* nn_idx,
                             int32_t* count, palmad_stats* stats, void* stream);
 
+/* Result of palmad_autotune() (host struct). */
+typedef struct {
+    int32_t evaluated;       /* configurations timed */
+    int32_t probe_lengths;   /* lengths per series searched by each probe */
+    double base_seconds;     /* best probe time of the options passed in */
+    double best_seconds;     /* best probe time of the options returned */
+} palmad_tune_report;
+
+/*
+ * Bytes of device workspace palmad_autotune() needs (the probe's search
+ * workspace plus its result rows).  Arguments as palmad_autotune().
+ */
+int palmad_autotune_workspace_size(int32_t B, const int64_t* offsets, const int32_t* minL,
+                                   const int32_t* maxL, int32_t k, int32_t probe_lengths,
+                                   size_t* bytes);
+
+/*
+ * Pick the tile geometry of the sweeps (not in the paper): row-tile heights
+ * of the three passes, near_cols, chunk_cols and far_grid, by timing the
+ * search itself on a probe, one coordinate at a time starting from `base`
+ * (dist_bits, guard and flags are kept).  The probe searches every series
+ * over its first probe_lengths lengths (fewer if its range is shorter);
+ * each configuration runs once untimed, then `reps` times, and its best
+ * wall time counts.  The tile geometry changes the order of floating-point
+ * work only: results agree within the documented tolerance for any choice.
+ *
+ *   values, offsets, B, minL, maxL, k  as palmad_discords_batched() (B = 1
+ *            with offsets {0, n} for a single series).
+ *   base     options to start from (NULL = defaults).
+ *   probe_lengths  >= 1 (values above a series' range are clipped).
+ *   reps     timed runs per configuration, >= 1.
+ *   workspace  device, >= palmad_autotune_workspace_size() bytes.
+ *   best     host: the chosen options.
+ *   report   host, optional (NULL).
+ */
+int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offsets, int32_t B,
+                    const int32_t* minL, const int32_t* maxL, int32_t k,
+                    const palmad_options* base, int32_t probe_lengths, int32_t reps,
+                    void* workspace, size_t ws_bytes, palmad_options* best,
+                    palmad_tune_report* report, void* stream);
+
 /*
  * One range search at a single length m and range r (the DRAG problem of
  * Alg. 2 as parallelised in Sec. 3.2-3.3): every subsequence whose nearest

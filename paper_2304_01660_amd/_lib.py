@@ -61,6 +61,15 @@ class Stats(ctypes.Structure):
         return d
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("evaluated", ctypes.c_int32),
+        ("probe_lengths", ctypes.c_int32),
+        ("base_seconds", ctypes.c_double),
+        ("best_seconds", ctypes.c_double),
+    ]
+
+
 FLAG_TIME_KERNELS = 1
 FLAG_NO_GRAPH = 2
 KERNEL_CLASSES = ("select_near", "select_far", "refine", "polish")
@@ -93,6 +102,11 @@ SIGNATURES = {
     "palmad_discords_batched": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32,
                                                ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
                                                _vp, _vp, _vp, _vp, ctypes.POINTER(Stats), _vp]),
+    "palmad_autotune_workspace_size": (ctypes.c_int, [_i32, _vp, _vp, _vp, _i32, _i32,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "palmad_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32,
+                                       ctypes.POINTER(Options), _i32, _i32, _vp, ctypes.c_size_t,
+                                       ctypes.POINTER(Options), ctypes.POINTER(TuneReport), _vp]),
     "palmad_range_discords": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.c_double,
                                              ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
                                              _vp, ctypes.POINTER(_i64), ctypes.POINTER(Stats),

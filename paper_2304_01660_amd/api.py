@@ -188,6 +188,50 @@ def discords_batched(series, minL, maxL, k: int, *, dist_bits: int = 0, guard: f
     return res
 
 
+TUNED_KEYS = ("dist_bits", "guard", "near_cols", "chunk_cols", "rows_near", "rows_far",
+              "rows_refine", "far_grid")
+
+
+def autotune(series, minL, maxL, k: int, *, probe_lengths: int = 6, reps: int = 2, **base):
+    """Pick the sweeps' tile geometry by timing probes of the search itself.
+
+    ``series`` is one 1-D GPU tensor or a list of them (as for
+    :func:`discords_batched`); ``base`` holds starting options.  Returns
+    (options dict for :func:`discords` / :func:`discords_batched`, report).
+    """
+    if isinstance(series, torch.Tensor):
+        parts = [_series(series)]
+    else:
+        parts = [_series(t) for t in series]
+    values = torch.cat(parts) if len(parts) > 1 else parts[0]
+    dev = values.device
+    B = len(parts)
+    lo = [int(minL)] * B if isinstance(minL, int) else [int(v) for v in minL]
+    hi = [int(maxL)] * B if isinstance(maxL, int) else [int(v) for v in maxL]
+    offs = (ctypes.c_int64 * (B + 1))()
+    for b, t in enumerate(parts):
+        offs[b + 1] = offs[b] + int(t.shape[0])
+    c_lo = (ctypes.c_int32 * B)(*lo)
+    c_hi = (ctypes.c_int32 * B)(*hi)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_autotune_workspace_size(B, offs, c_lo, c_hi, int(k),
+                                                         int(probe_lengths),
+                                                         ctypes.byref(nbytes)))
+    ws = _workspace(int(nbytes.value), dev)
+    o = _lib.make_options(**base)
+    best = _lib.Options()
+    rep = _lib.TuneReport()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_autotune(ctx, ctypes.c_void_p(values.data_ptr()), offs, B, c_lo, c_hi,
+                                    int(k), ctypes.byref(o), int(probe_lengths), int(reps),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    ctypes.byref(best), ctypes.byref(rep), _stream(dev))
+    _lib.check(rc, ctx)
+    opts = {key: getattr(best, key) for key in TUNED_KEYS}
+    report = {f: getattr(rep, f) for f, _ in rep._fields_}
+    return opts, report
+
+
 def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, guard: float = 0.0,
                    near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False,
                    time_kernels: bool = False, rows_near: int = 0, rows_far: int = 0,

@@ -462,6 +462,59 @@ size_t backward_bytes(int64_t n, int64_t K, int32_t maxm, Plan* p, int64_t* nblk
     return p->total + al256((size_t)std::max<int64_t>(K, 1) * (size_t)*nblk * 2 * sizeof(double));
 }
 
+// ---- autotuner ----
+
+// The probe: every series over its first `probe` lengths.
+struct Probe {
+    std::vector<int64_t> n;
+    std::vector<int32_t> lo, hi;
+    Plan plan;
+    size_t off_out, total;
+    int64_t rows, lrows;
+};
+
+void make_probe(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL, int32_t k,
+                int32_t probe, Probe* pr)
+{
+    pr->n.assign(n, n + B);
+    pr->lo.assign(minL, minL + B);
+    pr->hi.resize(B);
+    pr->rows = pr->lrows = 0;
+    for (int b = 0; b < B; ++b) {
+        pr->hi[b] = std::min<int32_t>(maxL[b], minL[b] + probe - 1);
+        const int64_t L = (int64_t)pr->hi[b] - minL[b] + 1;
+        pr->rows += L * k;
+        pr->lrows += L;
+    }
+    make_plan(B, pr->n.data(), pr->lo.data(), pr->hi.data(), k,
+              cfg_of(default_opts(), nullptr), &pr->plan);
+    pr->off_out = pr->plan.total;
+    pr->total = pr->off_out + al256((size_t)pr->rows * (8 + 4 + 8 + 8) + (size_t)pr->lrows * 4 + 1024);
+}
+
+// Best wall time of `reps` searches of the probe under options `o` (after
+// one untimed run, which also captures the round graph).
+int time_probe(palmad_ctx* ctx, const Probe& pr, int32_t k, const Opts& o, void* ws,
+               const std::vector<const double*>& tin, const std::vector<Outputs>& outs, int reps,
+               void* stream, double* best)
+{
+    Plan p;  // the prefix tables depend on the tile geometry
+    make_plan(pr.plan.B, pr.n.data(), pr.lo.data(), pr.hi.data(), k, cfg_of(o, nullptr), &p);
+    const int rc0 = check_grid(ctx, p);
+    if (rc0) return rc0;
+    double bs = 1e300;
+    for (int r = 0; r <= reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = search(ctx, p, o, ws, tin.data(), outs.data(), nullptr, stream);
+        if (rc) return rc;
+        const double dt =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (r > 0) bs = std::min(bs, dt);
+    }
+    *best = bs;
+    return PALMAD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -736,6 +789,123 @@ int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_
     }
     HIP_TRY(hipStreamSynchronize(ctx->work));
     return leave(ctx, stream);
+}
+
+int palmad_autotune_workspace_size(int32_t B, const int64_t* offsets, const int32_t* minL,
+                                   const int32_t* maxL, int32_t k, int32_t probe_lengths,
+                                   size_t* bytes)
+{
+    if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
+    if (probe_lengths < 1) return fail(nullptr, PALMAD_EINVAL, "probe_lengths must be >= 1");
+    std::vector<int64_t> n;
+    const int rc = validate_batch(nullptr, B, offsets, minL, maxL, k, &n);
+    if (rc) return rc;
+    Probe pr;
+    make_probe(B, n.data(), minL, maxL, k, probe_lengths, &pr);
+    *bytes = pr.total;
+    return PALMAD_OK;
+}
+
+int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offsets, int32_t B,
+                    const int32_t* minL, const int32_t* maxL, int32_t k,
+                    const palmad_options* base, int32_t probe_lengths, int32_t reps,
+                    void* workspace, size_t ws_bytes, palmad_options* best,
+                    palmad_tune_report* report, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!values || !best) return fail(ctx, PALMAD_EINVAL, "null values or best");
+    if (probe_lengths < 1) return fail(ctx, PALMAD_EINVAL, "probe_lengths must be >= 1");
+    if (reps < 1) return fail(ctx, PALMAD_EINVAL, "reps must be >= 1");
+    std::vector<int64_t> n;
+    int rc = validate_batch(ctx, B, offsets, minL, maxL, k, &n);
+    if (rc) return rc;
+    Opts cur;
+    rc = read_opts(ctx, base, &cur);
+    if (rc) return rc;
+    cur.flags &= ~(unsigned int)PALMAD_FLAG_TIME_KERNELS;
+    Probe pr;
+    make_probe(B, n.data(), minL, maxL, k, probe_lengths, &pr);
+    rc = check_grid(ctx, pr.plan);
+    if (rc) return rc;
+    rc = check_ws(ctx, workspace, ws_bytes, pr.total);
+    if (rc) return rc;
+    // result rows of the probe live after its search workspace
+    char* o = (char*)workspace + pr.off_out;
+    int64_t* idx = (int64_t*)o;
+    int64_t* nnidx = idx + pr.rows;
+    double* nn = (double*)(nnidx + pr.rows);
+    int32_t* len = (int32_t*)(nn + pr.rows);
+    int32_t* cnt = len + pr.rows;
+    std::vector<const double*> tin(B);
+    std::vector<Outputs> outs(B);
+    int64_t row = 0, lrow = 0;
+    for (int b = 0; b < B; ++b) {
+        tin[b] = values + offsets[b];
+        const int64_t L = (int64_t)pr.hi[b] - pr.lo[b] + 1;
+        outs[b] = {idx + row, len + row, nn + row, nnidx + row, cnt + lrow};
+        row += L * k;
+        lrow += L;
+    }
+    // resolve the defaults to concrete values so every axis has a value
+    {
+        const SweepCfg c = cfg_of(cur, nullptr);
+        cur.rows_near = 64 * c.q_near;
+        cur.rows_far = 64 * c.q_far;
+        cur.rows_refine = 64 * c.q_ref;
+    }
+    double t_best = 0.0;
+    rc = time_probe(ctx, pr, k, cur, workspace, tin, outs, reps, stream, &t_best);
+    if (rc) return rc;
+    const double t_base = t_best;
+    int evaluated = 1;
+    static const int rows_v[] = {128, 256, 512};
+    static const int chunk_v[] = {256, 512, 1024, 2048};
+    static const int near_v[] = {1024, 2048, 4096, 8192};
+    static const int grid_v[] = {1024, 2048, 3072, 4096, 8192};
+    struct Axis {
+        int* field;
+        const int* vals;
+        int count;
+    };
+    const Axis axes[] = {
+        {&cur.chunk_cols, chunk_v, 4}, {&cur.near_cols, near_v, 4},  {&cur.rows_near, rows_v, 3},
+        {&cur.rows_far, rows_v, 3},    {&cur.rows_refine, rows_v, 3}, {&cur.far_grid, grid_v, 5},
+    };
+    for (const Axis& ax : axes) {
+        const int keep = *ax.field;
+        int best_v = keep;
+        for (int i = 0; i < ax.count; ++i) {
+            if (ax.vals[i] == keep) continue;
+            *ax.field = ax.vals[i];
+            double t = 0.0;
+            rc = time_probe(ctx, pr, k, cur, workspace, tin, outs, reps, stream, &t);
+            if (rc) return rc;
+            ++evaluated;
+            if (t < t_best) {
+                t_best = t;
+                best_v = ax.vals[i];
+            }
+        }
+        *ax.field = best_v;
+    }
+    palmad_options r = {};
+    r.dist_bits = cur.dist_bits;
+    r.guard = cur.guard;
+    r.near_cols = cur.near_cols;
+    r.chunk_cols = cur.chunk_cols;
+    r.flags = base ? base->flags : 0u;
+    r.rows_near = cur.rows_near;
+    r.rows_far = cur.rows_far;
+    r.rows_refine = cur.rows_refine;
+    r.far_grid = cur.far_grid;
+    *best = r;
+    if (report) {
+        report->evaluated = evaluated;
+        report->probe_lengths = probe_lengths;
+        report->base_seconds = t_base;
+        report->best_seconds = t_best;
+    }
+    return PALMAD_OK;
 }
 
 }  // extern "C"

@@ -151,3 +151,31 @@ def test_config4_batched_full_size():
             for i in rng.integers(0, w.n - m + 1, size=4):
                 d, _ = oracle.nn_row(w.T, m, int(i))
                 assert d <= nn[q] * (1 + 1e-9), (b, m, i, d, nn[q])
+
+
+def test_autotune_returns_valid_options_and_same_discords():
+    """The tuner times the search on a probe and returns tile geometry; the
+    search under any geometry reports the same discords (within the
+    floating-point tolerance, checked against brute force)."""
+    dev = _dev()
+    from paper_2304_01660_amd import api
+    cases = _small_batch()[:4]
+    vals = [torch.from_numpy(T).to(dev) for T, _, _ in cases]
+    lo = [c[1] for c in cases]
+    hi = [c[2] for c in cases]
+    _say("autotune small batch")
+    opts, rep = api.autotune(vals, lo, hi, 2, probe_lengths=3, reps=1)
+    _say("autotune", opts, rep)
+    assert rep["evaluated"] >= 10
+    assert rep["best_seconds"] <= rep["base_seconds"]
+    assert opts["rows_near"] in (128, 256, 512) and opts["rows_far"] in (128, 256, 512)
+    assert opts["rows_refine"] in (128, 256, 512)
+    assert opts["chunk_cols"] >= 64 and opts["near_cols"] >= 64 and opts["far_grid"] >= 1
+    res = api.discords_batched(vals, lo, hi, 2, **opts)
+    for b, (T, l, h) in enumerate(cases):
+        check_against_profiles(T, res[b], l, h, 2)
+    # single series form
+    opts1, rep1 = api.autotune(vals[0], lo[0], hi[0], 2, probe_lengths=2, reps=1, dist_bits=64)
+    assert opts1["dist_bits"] == 64
+    out = api.discords(vals[0], lo[0], hi[0], 2, **opts1)
+    check_against_profiles(cases[0][0], out, lo[0], hi[0], 2)
