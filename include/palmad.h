@@ -103,6 +103,9 @@ typedef struct {
     uint64_t kernel_evals[PALMAD_KERNEL_CLASSES];    /* pair evaluations per class */
     uint64_t kernel_launches[PALMAD_KERNEL_CLASSES]; /* launches per class */
     double kernel_ms[PALMAD_KERNEL_CLASSES];         /* device time per class (flag set) */
+    uint64_t rows_after_near; /* live subsequences after the first selection pass, summed
+                                 over the range searches that prune */
+    uint64_t rows_after_far;  /* live subsequences entering refinement, summed likewise */
 } palmad_stats;
 
 typedef struct palmad_ctx palmad_ctx;

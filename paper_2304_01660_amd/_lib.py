@@ -51,6 +51,8 @@ class Stats(ctypes.Structure):
         ("kernel_evals", ctypes.c_uint64 * 4),
         ("kernel_launches", ctypes.c_uint64 * 4),
         ("kernel_ms", ctypes.c_double * 4),
+        ("rows_after_near", ctypes.c_uint64),
+        ("rows_after_far", ctypes.c_uint64),
     ]
 
     def as_dict(self):

@@ -184,6 +184,7 @@ struct Plan {
     int64_t totals[PFX_KINDS];
     std::vector<int64_t> pfx;  // [PFX_KINDS][B+1]
     int32_t maxL_all;
+    int64_t Nmax_all;
 };
 
 void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL, int32_t k,
@@ -195,9 +196,10 @@ void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL
     p->off_pfx = al256(sizeof(SeriesDev) * (size_t)B);
     p->off_rem = al256(p->off_pfx + sizeof(int64_t) * (size_t)PFX_KINDS * (size_t)(B + 1));
     p->off_sums = p->off_rem + 64;
-    size_t o = al256(p->off_sums + 8 * sizeof(unsigned long long));
+    size_t o = al256(p->off_sums + 16 * sizeof(unsigned long long));
     p->pfx.assign((size_t)PFX_KINDS * (B + 1), 0);
     p->maxL_all = 0;
+    p->Nmax_all = 0;
     for (int b = 0; b < B; ++b) {
         make_layout(n[b], minL[b], maxL[b], k, &p->lay[b]);
         p->base[b] = o;
@@ -207,6 +209,7 @@ void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL
         for (int q = 0; q < PFX_KINDS; ++q)
             p->pfx[(size_t)q * (B + 1) + b + 1] = p->pfx[(size_t)q * (B + 1) + b] + blk[q];
         p->maxL_all = std::max(p->maxL_all, maxL[b]);
+        p->Nmax_all = std::max(p->Nmax_all, p->lay[b].Nmax);
     }
     for (int q = 0; q < PFX_KINDS; ++q) p->totals[q] = p->pfx[(size_t)q * (B + 1) + B];
     p->total = o;
@@ -255,6 +258,7 @@ int upload(palmad_ctx* ctx, const Plan& p, void* ws, const double* const* Tin, c
         bt->pfx[q] = (const int64_t*)((char*)ws + p.off_pfx) + (size_t)q * (p.B + 1);
     bt->B = p.B;
     bt->maxL_all = p.maxL_all;
+    bt->Nmax_all = p.Nmax_all;
     bt->remaining = (int32_t*)((char*)ws + p.off_rem);
     bt->sums = (unsigned long long*)((char*)ws + p.off_sums);
     return PALMAD_OK;
@@ -320,7 +324,8 @@ int prepare(palmad_ctx* ctx, const Batch& bt, const Plan& p)
 std::string graph_key(const Batch& bt, const SweepCfg& c, const Plan& p)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%a|", (void*)bt.s, bt.B, bt.maxL_all,
+    snprintf(buf, sizeof buf, "%p|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%a|", (void*)bt.s, bt.B,
+             bt.maxL_all, (long long)bt.Nmax_all,
              c.near_cols, c.chunk_cols, c.dist_bits, c.far_grid, c.q_near, c.q_far, c.q_ref,
              (double)c.guard);
     std::string k = buf;
@@ -377,7 +382,7 @@ int gather_stats(palmad_ctx* ctx, const Batch& bt, const KernelTimer& t, double 
     if (!stats) return PALMAD_OK;
     HIP_TRY(launch_sum_stats(bt, bt.sums, ctx->work));
     unsigned long long* h = (unsigned long long*)(ctx->pinned + 16);
-    HIP_TRY(hipMemcpyAsync(h, bt.sums, 7 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(h, bt.sums, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            ctx->work));
     HIP_TRY(hipStreamSynchronize(ctx->work));
     std::memset(stats, 0, sizeof *stats);
@@ -390,6 +395,8 @@ int gather_stats(palmad_ctx* ctx, const Batch& bt, const KernelTimer& t, double 
     stats->kernel_evals[PALMAD_KERNEL_SELECT_FAR] = h[6];
     stats->kernel_evals[PALMAD_KERNEL_REFINE] = h[1];
     stats->kernel_evals[PALMAD_KERNEL_POLISH] = h[2];
+    stats->rows_after_near = h[7];
+    stats->rows_after_far = h[8];
     stats->seconds = secs;
     for (int k = 0; k < KCLASSES; ++k) {
         stats->kernel_launches[k] = t.launches[k];
@@ -860,7 +867,7 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
     int evaluated = 1;
     static const int rows_v[] = {128, 256, 512};
     static const int chunk_v[] = {256, 512, 1024, 2048};
-    static const int near_v[] = {1024, 2048, 4096, 8192};
+    static const int near_v[] = {2048, 8192, 32768, 1 << 30};
     static const int grid_v[] = {1024, 2048, 3072, 4096, 8192};
     struct Axis {
         int* field;

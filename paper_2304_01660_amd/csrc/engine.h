@@ -21,10 +21,15 @@ constexpr int R_MAX = 512;   // tallest row tile (64 lanes x 8 rows)
 constexpr int KP_EXTRA = 4;  // candidates polished beyond k
 constexpr int K_MAX = 64;
 constexpr int KP_MAX = K_MAX + KP_EXTRA;
-constexpr int POLISH_BLOCK = 256;
+constexpr int POLISH_BLOCK = 128;
+constexpr int POLISH_CPT = 4;  // columns per polish thread
+constexpr int POLISH_COLS = POLISH_BLOCK * POLISH_CPT;
 constexpr int TOPK_BLOCK = 1024;
 constexpr int RED_BLOCKS = 256;   // series reductions: blocks of 256 threads
 constexpr int MAX_ATTEMPTS = 5000;
+// A round whose selection leaves at most this many live subsequences skips
+// the refinement sweep: the exact pass evaluates all of them directly.
+constexpr int DIRECT_MAX = KP_MAX;
 
 // Device-resident control block of one series (the MERLIN state of Alg. 1
 // plus the work counters of the current round).
@@ -55,10 +60,12 @@ struct Ctrl {
     unsigned long long ctr_sel, ctr_ref;  // work-queue heads (items: chunk-major)
     uint32_t nsurv;
     uint32_t ncand;
+    uint32_t live_ref;     // live subsequences entering refinement this round
     int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
     // counters accumulated over the call
     unsigned long long evals_sel, evals_ref, evals_pol, rounds, survivors;
     unsigned long long evals_near, evals_far;
+    unsigned long long rows_near, rows_far;  // live rows entering the split / refinement passes
 };
 
 // Static geometry and buffers of one series (host computes, device reads).
@@ -69,8 +76,10 @@ struct SeriesDev {
     // input and workspace buffers
     const double* Tin;   // caller's series
     double* T;           // padded FP64 copy
-    double* mu;          // [Npad+64]
+    double* mu;          // [Npad+64], lengths with m - minL even
     double* var;         // [Npad+64]
+    double* mu2;         // [Npad+64], lengths with m - minL odd
+    double* var2;        // [Npad+64]
     float* df32;         // helpers, FP32 (SoA, Npad+64 each)
     float* dg32;
     float* inv32;
@@ -81,9 +90,9 @@ struct SeriesDev {
     unsigned long long* rho;     // ordered-bits row max correlation [Npad]
     int32_t* tsel;       // live selection tiles
     int32_t* tref;       // live refinement tiles
-    int32_t* surv;       // survivor rows
     int64_t* cand;       // polished candidates [KP_MAX]
     double* part;        // polish partials [KP_MAX * npart * 2 + tail]
+    double* xc;          // centred candidate windows [KP_MAX][maxL + 8], then their sums
     double* hist;        // nnDist history per length [L]
     double* red;         // reduction scratch [2 * RED_BLOCKS]
     Ctrl* ctrl;
@@ -99,8 +108,8 @@ struct SeriesDev {
 struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
-    size_t off_T, off_mu, off_var, off_h32, off_h64, off_alive, off_rho, off_tsel, off_tref,
-        off_surv, off_cand, off_part, off_hist, off_ctrl, off_red, total;
+    size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho,
+        off_tsel, off_tref, off_cand, off_part, off_xc, off_hist, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
 SeriesDev carve(void* base, const Layout& lay);
@@ -112,7 +121,6 @@ enum PrefixKind {
     PFX_NEAR,       // first-pass selection items: tiles x chunks
     PFX_TSEL,       // blocks of 256 over selection tiles (compaction)
     PFX_TREF,       // blocks of 256 over refinement tiles (compaction)
-    PFX_WORDS,      // blocks of 256 over bitmap words (survivors)
     PFX_POLISH,     // blocks of 256 columns (polish)
     PFX_KINDS
 };
@@ -122,8 +130,9 @@ struct Batch {
     const int64_t* pfx[PFX_KINDS];   // device arrays [B+1]
     int32_t B;
     int32_t maxL_all;                // largest length over the batch (LDS sizing)
+    int64_t Nmax_all;                // most subsequences of any series
     int32_t* remaining;              // device [2]: series with work left, series in error
-    unsigned long long* sums;        // device [8]: counters summed over the batch
+    unsigned long long* sums;        // device [9]: counters summed over the batch
 };
 
 // Optional per-kernel event timing (host side).
@@ -164,7 +173,7 @@ hipError_t launch_range_out(const Batch& bt, int64_t N, unsigned long long* aliv
                             double* nn_out, hipStream_t st);
 hipError_t launch_stats_to(const Batch& bt, int32_t minL, int32_t m, const int64_t* total,
                            hipStream_t st);
-// Per-series counters summed over the batch: 7 values (see k_sum_stats).
+// Per-series counters summed over the batch: 9 values (see k_sum_stats).
 hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_t st);
 // out[0] = series holding NaN/Inf, out[1] = the first of them (or -1).
 hipError_t launch_nonfinite(const Batch& bt, int32_t* out, hipStream_t st);

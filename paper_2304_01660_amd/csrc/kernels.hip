@@ -43,6 +43,7 @@ namespace palmad {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+constexpr int PF_T = 4;  // 64-value groups of a block's T segment prefetched into registers
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l <- lane l-1
 constexpr int DPP_WAVE_ROL1 = 0x134;  // lane l <- lane l+1 (63 <- 0)
 
@@ -156,202 +157,213 @@ __device__ __forceinline__ unsigned long long pair_count(long long ilo, long lon
 }
 
 // ---------------------------------------------------------------------------
-// round preparation: MERLIN's walk over the lengths (Alg. 1)
+// round preparation: MERLIN's walk over the lengths and its choice of r
+// (Alg. 1), for every series (one block)
 // ---------------------------------------------------------------------------
 // Advance every series: the first round starts at minL; after a successful
 // round the next length starts; after a failed one the same length is
-// searched again with the r that k_round_end lowered.
-__global__ void k_round_prep(SeriesDev* S, int B)
+// searched again with the r that k_round_end lowered.  Then set the range of
+// this round, its pruning threshold and reset the round's work counters.
+// rem[0] (series with work left after the round, counted by k_round_end) and
+// rem[1] (series that gave up) start at zero here.
+__device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const SeriesDev& s = S[b];
-    Ctrl* c = s.ctrl;
-    if (c->finished) {
-        c->active = 0;
-        return;
-    }
-    if (!c->started) {
-        c->started = 1;
-        c->m = s.minL;
-        c->li = 0;
-        c->attempt = 0;
-        c->new_len = 2;
-        c->done = 0;
-        c->active = 1;
-        return;
-    }
-    if (c->done) {
-        if (c->m >= s.maxL) {
-            c->finished = 1;
-            c->active = 0;
-            return;
-        }
-        c->m += 1;
-        c->li += 1;
-        c->attempt = 0;
-        c->new_len = 1;
-        c->done = 0;
-    } else {
-        c->attempt += 1;
-        c->new_len = 0;
-        if (c->attempt >= MAX_ATTEMPTS) {
-            c->error = 1;
-            c->finished = 1;
-            c->active = 0;
-            return;
+    const int li = c->li;
+    const int32_t m = c->m;
+    if (c->attempt == 0 && c->mode != 3) {
+        if (li == 0) {
+            c->mode = 0;
+            c->r = 2.0 * sqrt((double)s.minL);
+        } else if (li <= 4) {
+            c->mode = 1;
+            c->r = 0.99 * s.hist[li - 1];
+        } else {
+            double mean = 0.0;
+            for (int q = 1; q <= 5; ++q) mean += s.hist[li - q];
+            mean /= 5.0;
+            double v = 0.0;
+            for (int q = 1; q <= 5; ++q) {
+                const double d = s.hist[li - q] - mean;
+                v += d * d;
+            }
+            c->step = sqrt(v / 5.0);
+            c->r = mean - 2.0 * c->step;
+            c->mode = 2;
         }
     }
-    c->active = 1;
-}
-
-// ---------------------------------------------------------------------------
-// per-length statistics (Eq. (4) at minL, Eq. (7)-(8) after) and helpers
-// ---------------------------------------------------------------------------
-__global__ void k_stats(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
-{
-    const int b = series_of(pfx, B, blockIdx.x);
-    const SeriesDev& s = S[b];
-    Ctrl* c = s.ctrl;
-    if (!c->active || c->new_len == 0) return;
-    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
-    if (i == 0) {
+    const double r = c->r;
+    c->prune = r > 0.0 ? 1 : 0;
+    c->thr64 = r > 0.0 ? 1.0 - r * r / (2.0 * (double)m) : 2.0;
+    c->thr_sel = c->thr64 + (double)guard;
+    // round up: an FP32 threshold must never prune more than thr_sel
+    c->thr32 = __double2float_ru(c->thr_sel);
+    c->nlive_sel = c->maxc_sel = 0;
+    c->nlive_ref = c->maxc_ref = 0;
+    c->ctr_sel = c->ctr_ref = 0ull;
+    c->nsurv = 0;
+    c->ncand = 0;
+    c->live_ref = 0;
+    if (c->new_len) {
         c->flat_min = 0x7fffffffffffffffll;
         c->flat_max = -1;
     }
-    if (i >= s.Npad + 64) return;
-    const double* __restrict__ T = s.T;
-    const int32_t m = c->m;
-    if (c->new_len == 2) {
-        // Eq. (4): direct two-pass statistics at the first length
-        const int64_t N = s.n - m + 1;
-        if (i >= N) {
-            s.mu[i] = 0.0;
-            s.var[i] = 0.0;
-            return;
-        }
-        double acc = 0.0;
-        for (int k = 0; k < m; ++k) acc += T[i + k];
-        const double mean = acc / (double)m;
-        double q = 0.0;
-        for (int k = 0; k < m; ++k) {
-            const double d = T[i + k] - mean;
-            q += d * d;
-        }
-        s.mu[i] = mean;
-        s.var[i] = q / (double)m;
-    } else {
-        // Eq. (7)-(8): length m from length m-1, in place
-        const int32_t mo = m - 1;
-        const int64_t N1 = s.n - mo;  // windows of length m
-        if (i >= N1) {
-            s.mu[i] = 0.0;
-            s.var[i] = 0.0;
-            return;
-        }
-        const double t = T[i + mo];
-        const double mu0 = s.mu[i];
-        const double dm = (double)mo;
-        const double d = mu0 - t;
-        s.mu[i] = (dm * mu0 + t) / (dm + 1.0);
-        s.var[i] = dm / (dm + 1.0) * (s.var[i] + d * d / (dm + 1.0));
+}
+
+__global__ void k_round_prep(SeriesDev* S, int B, float guard, int32_t* rem)
+{
+    if (threadIdx.x == 0) {
+        rem[0] = 0;
+        rem[1] = 0;
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const SeriesDev& s = S[b];
+        Ctrl* c = s.ctrl;
+        if (c->finished) {
+            c->active = 0;
+            continue;
+        }
+        if (!c->started) {
+            c->started = 1;
+            c->m = s.minL;
+            c->li = 0;
+            c->attempt = 0;
+            c->new_len = 2;
+        } else if (c->done) {
+            if (c->m >= s.maxL) {
+                c->finished = 1;
+                c->active = 0;
+                continue;
+            }
+            c->m += 1;
+            c->li += 1;
+            c->attempt = 0;
+            c->new_len = 1;
+        } else {
+            c->attempt += 1;
+            c->new_len = 0;
+            if (c->attempt >= MAX_ATTEMPTS) {
+                c->error = 1;
+                c->finished = 1;
+                c->active = 0;
+                atomicAdd(&rem[1], 1);
+                continue;
+            }
+        }
+        c->done = 0;
+        c->active = 1;
+        begin_range(s, c, guard);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-length statistics (Eq. (4) at minL, Eq. (7)-(8) after), the column and
+// row helpers, and the per-round reset of the bitmap and row maxima
+// ---------------------------------------------------------------------------
+// Statistics live in two buffers used alternately from one length to the
+// next (mu/var for even m - minL, mu2/var2 for odd), so every thread can
+// read the previous length's values of its own window and of the next one.
+__device__ __forceinline__ const double* cur_mu(const SeriesDev& s, const Ctrl* c)
+{
+    return (c->li & 1) ? s.mu2 : s.mu;
+}
+__device__ __forceinline__ const double* cur_var(const SeriesDev& s, const Ctrl* c)
+{
+    return (c->li & 1) ? s.var2 : s.var;
+}
+
+// A round whose selection left at most DIRECT_MAX live subsequences: the
+// refinement sweep is skipped and the exact pass evaluates every one of them.
+__device__ __forceinline__ bool direct_round(const Ctrl* c) { return c->live_ref <= DIRECT_MAX; }
+
+// Mean and variance of window p at length m: two passes (Eq. (4)).
+__device__ __forceinline__ void direct_stats(const double* __restrict__ T, int64_t p, int32_t m,
+                                             double& mean, double& var)
+{
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += T[p + k];
+    mean = acc / (double)m;
+    double q = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double d = T[p + k] - mean;
+        q += d * d;
+    }
+    var = q / (double)m;
+}
+
+// Eq. (7)-(8): window p from length m-1 (mean mu0, variance v0) to m.
+__device__ __forceinline__ void grow_stats(const double* __restrict__ T, int64_t p, int32_t m,
+                                           double mu0, double v0, double& mean, double& var)
+{
+    const int32_t mo = m - 1;
+    const double t = T[p + mo];
+    const double dm = (double)mo;
+    const double d = mu0 - t;
+    mean = (dm * mu0 + t) / (dm + 1.0);
+    var = dm / (dm + 1.0) * (v0 + d * d / (dm + 1.0));
 }
 
 // df[i] = (t_{i+m} - t_i)/2, dg[i] = (t_{i+m} - mu_{i+1}) + (t_i - mu_i) for
 // i < N-1 (zero beyond), inv[i] = 1/(sqrt(m) sigma_i) for non-flat i < N.
-__global__ void k_helpers(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
-{
-    const int b = series_of(pfx, B, blockIdx.x);
-    const SeriesDev& s = S[b];
-    Ctrl* c = s.ctrl;
-    if (!c->active || c->new_len == 0) return;
-    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= s.Npad + 64) return;
-    const int32_t m = c->m;
-    const int64_t N = s.n - m + 1;
-    const double* __restrict__ T = s.T;
-    double df = 0.0, dg = 0.0, inv = 0.0;
-    if (i < N - 1) {
-        const double a = T[i + m], e = T[i];
-        df = (a - e) * 0.5;
-        dg = (a - s.mu[i + 1]) + (e - s.mu[i]);
-    }
-    if (i < N) {
-        const double sg = sqrt(s.var[i]);
-        if (sg <= c->flat_eps) {
-            atomicMin((long long*)&c->flat_min, (long long)i);
-            atomicMax((long long*)&c->flat_max, (long long)i);
-        } else {
-            inv = 1.0 / (sqrt((double)m) * sg);
-        }
-    }
-    s.df64[i] = df;
-    s.dg64[i] = dg;
-    s.inv64[i] = inv;
-    s.df32[i] = (float)df;
-    s.dg32[i] = (float)dg;
-    s.inv32[i] = (float)inv;
-}
-
-// ---------------------------------------------------------------------------
-// round control (MERLIN's r, Alg. 1) and per-round reset
-// ---------------------------------------------------------------------------
-__global__ void k_round_begin(SeriesDev* S, int B, const int64_t* __restrict__ pfx, float guard)
+__global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
 {
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
-    const int64_t g = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
     const int32_t m = c->m;
-    if (g == 0) {
-        const int li = c->li;
-        if (c->attempt == 0) {
-            c->done = 0;
-            if (c->mode != 3) {
-                if (li == 0) {
-                    c->mode = 0;
-                    c->r = 2.0 * sqrt((double)s.minL);
-                } else if (li <= 4) {
-                    c->mode = 1;
-                    c->r = 0.99 * s.hist[li - 1];
-                } else {
-                    double mean = 0.0;
-                    for (int q = 1; q <= 5; ++q) mean += s.hist[li - q];
-                    mean /= 5.0;
-                    double v = 0.0;
-                    for (int q = 1; q <= 5; ++q) {
-                        const double d = s.hist[li - q] - mean;
-                        v += d * d;
-                    }
-                    c->step = sqrt(v / 5.0);
-                    c->r = mean - 2.0 * c->step;
-                    c->mode = 2;
-                }
+    const int64_t N = s.n - m + 1;
+    if (c->new_len && i < s.Npad + 64) {
+        const double* __restrict__ T = s.T;
+        const bool odd = (c->li & 1) != 0;
+        double* mu_n = odd ? s.mu2 : s.mu;
+        double* var_n = odd ? s.var2 : s.var;
+        const double* mu_o = odd ? s.mu : s.mu2;
+        const double* var_o = odd ? s.var : s.var2;
+        double m0 = 0.0, v0 = 0.0, m1 = 0.0, v1 = 0.0;
+        if (i < N) {
+            if (c->new_len == 2) {
+                direct_stats(T, i, m, m0, v0);
+                if (i + 1 < N) direct_stats(T, i + 1, m, m1, v1);
+            } else {
+                grow_stats(T, i, m, mu_o[i], var_o[i], m0, v0);
+                if (i + 1 < N) grow_stats(T, i + 1, m, mu_o[i + 1], var_o[i + 1], m1, v1);
             }
         }
-        const double r = c->r;
-        c->prune = r > 0.0 ? 1 : 0;
-        c->thr64 = r > 0.0 ? 1.0 - r * r / (2.0 * (double)m) : 2.0;
-        c->thr_sel = c->thr64 + (double)guard;
-        // round up: an FP32 threshold must never prune more than thr_sel
-        c->thr32 = __double2float_ru(c->thr_sel);
-        c->nlive_sel = c->maxc_sel = 0;
-        c->nlive_ref = c->maxc_ref = 0;
-        c->ctr_sel = c->ctr_ref = 0ull;
-        c->nsurv = 0;
-        c->ncand = 0;
+        mu_n[i] = m0;
+        var_n[i] = v0;
+        double df = 0.0, dg = 0.0, inv = 0.0;
+        if (i < N - 1) {
+            const double a = T[i + m], e = T[i];
+            df = (a - e) * 0.5;
+            dg = (a - m1) + (e - m0);
+        }
+        if (i < N) {
+            const double sg = sqrt(v0);
+            if (sg <= c->flat_eps) {
+                atomicMin((long long*)&c->flat_min, (long long)i);
+                atomicMax((long long*)&c->flat_max, (long long)i);
+            } else {
+                inv = 1.0 / (sqrt((double)m) * sg);
+            }
+        }
+        s.df64[i] = df;
+        s.dg64[i] = dg;
+        s.inv64[i] = inv;
+        s.df32[i] = (float)df;
+        s.dg32[i] = (float)dg;
+        s.inv32[i] = (float)inv;
     }
-    const int64_t N = s.n - m + 1;
-    if (g < s.nwords) {
-        const int64_t lo = g * 64;
+    // every round: all N subsequences start alive, row maxima at -inf
+    if (i < s.nwords) {
+        const int64_t lo = i * 64;
         unsigned long long bits = 0ull;
         if (lo + 64 <= N) bits = ~0ull;
         else if (lo < N) bits = (1ull << (N - lo)) - 1ull;
-        s.alive[g] = bits;
+        s.alive[i] = bits;
     }
-    if (g < s.Npad) s.rho[g] = 0x000fffffffffffffull;  // ordered bits of -inf
+    if (i < s.Npad) s.rho[i] = 0x000fffffffffffffull;  // ordered bits of -inf
 }
 
 // ---------------------------------------------------------------------------
@@ -429,30 +441,55 @@ struct alignas(4 * sizeof(F)) H4 {
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item, in doubles: xs[m+64] | win[m+128] | hs[256].
+// LDS of a sweep work item, in doubles: xs[m+64] | win[max(m+128, 64*PF_T)] | hs[256].
 // win holds the first column's centred window while the initial column is
 // computed, then the T segment of the current block.
-__host__ __device__ constexpr int sweep_hs_offset(int m) { return (2 * m + 192 + 3) & ~3; }
+__host__ __device__ constexpr int sweep_win_doubles(int m)
+{
+    return (m + 128 > 64 * PF_T) ? m + 128 : 64 * PF_T;
+}
+__host__ __device__ constexpr int sweep_hs_offset(int m) { return (m + 64 + sweep_win_doubles(m) + 3) & ~3; }
 __host__ __device__ constexpr size_t sweep_lds_doubles(int m) { return (size_t)(sweep_hs_offset(m) + 256); }
 
-// Stage the block starting at column j0 in LDS: one burst of independent
-// loads brings the T segment and the column helpers, then lane l computes
-// the exact top-boundary value B(j0 + l) = C(i0, j0 + l) from LDS.  hs[s]
-// then holds everything step s needs.
+// Staging of one block of 64 columns, software-pipelined: prefetch() issues
+// the global loads of a block into registers (the T segment up to
+// 64 * PF_T values, the column helpers, mu_j) and returns at once, so they
+// travel while the previous block is swept; commit() then writes them to
+// LDS (loading any longer remainder of the T segment directly), and lane l
+// computes the exact top-boundary value B(j0 + l) = C(i0, j0 + l) from LDS.
+// hs[s] then holds everything step s needs.
 template <typename F>
-__device__ __forceinline__ void stage_block(const double* __restrict__ T, const double* __restrict__ mu,
-                                            const F* __restrict__ df, const F* __restrict__ dg,
-                                            const F* __restrict__ inv, int32_t m, int64_t j0,
-                                            const double* xs, double Sx, double* win, H4<F>* hs)
+struct Prefetch {
+    double muj;
+    F df, dg, inv;
+    double tw[PF_T];
+};
+
+template <typename F>
+__device__ __forceinline__ void prefetch(Prefetch<F>& p, const double* __restrict__ T,
+                                         const double* __restrict__ mu, const F* __restrict__ df,
+                                         const F* __restrict__ dg, const F* __restrict__ inv,
+                                         int64_t j0)
+{
+    const int lane = threadIdx.x;
+    p.muj = mu[j0 + lane];
+    p.df = df[j0 + lane - 1];
+    p.dg = dg[j0 + lane - 1];
+    p.inv = inv[j0 + lane];
+#pragma unroll
+    for (int q = 0; q < PF_T; ++q) p.tw[q] = T[j0 + lane + 64 * q];
+}
+
+template <typename F>
+__device__ __forceinline__ void commit(const Prefetch<F>& p, const double* __restrict__ T,
+                                       int32_t m, int64_t j0, const double* xs, double Sx,
+                                       double* win, H4<F>* hs)
 {
     const int lane = threadIdx.x;
     __syncthreads();  // the previous block is done with win and hs
-    const double muj = mu[j0 + lane];
-    H4<F> h;
-    h.df = df[j0 + lane - 1];
-    h.dg = dg[j0 + lane - 1];
-    h.inv = inv[j0 + lane];
-    for (int t = lane; t < m + 68; t += 64) win[t] = T[j0 + t];
+#pragma unroll
+    for (int q = 0; q < PF_T; ++q) win[lane + 64 * q] = p.tw[q];
+    for (int t = lane + 64 * PF_T; t < m + 68; t += 64) win[t] = T[j0 + t];
     __syncthreads();
     const double* tw = win + lane;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -462,7 +499,11 @@ __device__ __forceinline__ void stage_block(const double* __restrict__ T, const 
         a2 = fma(xs[k + 2], tw[k + 2], a2);
         a3 = fma(xs[k + 3], tw[k + 3], a3);
     }
-    h.B = (F)((a0 + a1) + (a2 + a3) - muj * Sx);
+    H4<F> h;
+    h.df = p.df;
+    h.dg = p.dg;
+    h.inv = p.inv;
+    h.B = (F)((a0 + a1) + (a2 + a3) - p.muj * Sx);
     hs[lane] = h;
     __syncthreads();
 }
@@ -493,16 +534,19 @@ __device__ __forceinline__ void rows_from_bitmap(const unsigned long long* alive
 }
 
 // Publish rows dead locally but still set in the bitmap; absorb rows the
-// bitmap says are dead.  Returns true while some row of the tile is alive.
+// bitmap says are dead (`word`: the lane's bitmap word, loaded earlier so
+// that its latency overlaps the sweep).  Returns true while some row of the
+// tile is alive.
 template <int Q>
-__device__ __forceinline__ bool sync_rows(unsigned long long* alive, int64_t rbase,
-                                          unsigned long long (&dm)[Q])
+__device__ __forceinline__ bool sync_rows_with(unsigned long long* alive, int64_t rbase,
+                                               unsigned long long word,
+                                               unsigned long long (&dm)[Q])
 {
     const int lane = threadIdx.x;
     unsigned long long* wp = &alive[rbase >> 6];
     const int off = (int)(rbase & 63);
     const unsigned int msk = (Q >= 32) ? 0xffffffffu : ((1u << Q) - 1u);
-    const unsigned int live = (unsigned int)(load_word(wp) >> off) & msk;
+    const unsigned int live = (unsigned int)(word >> off) & msk;
     unsigned int mine = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) mine |= (unsigned int)((dm[q] >> lane) & 1ull) << q;
@@ -515,6 +559,13 @@ __device__ __forceinline__ bool sync_rows(unsigned long long* alive, int64_t rba
         all &= dm[q];
     }
     return __builtin_amdgcn_readfirstlane((int)(all != ~0ull)) != 0;
+}
+
+template <int Q>
+__device__ __forceinline__ bool sync_rows(unsigned long long* alive, int64_t rbase,
+                                          unsigned long long (&dm)[Q])
+{
+    return sync_rows_with<Q>(alive, rbase, load_word(&alive[rbase >> 6]), dm);
 }
 
 __device__ __forceinline__ void kill_columns(unsigned long long* alive, int64_t j0,
@@ -680,9 +731,14 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     unsigned long long ev = pair_count(i0, std::min<int64_t>(i0 + R, N), jbeg, 1, m, false);
     bool go = sync_rows<Q>(A.alive, rbase, dm);
     int64_t j = jbeg + 1;
+    Prefetch<F> pf;
+    if (go && j < jend) prefetch<F>(pf, A.T, A.mu, A.df, A.dg, A.inv, j);
     while (go && j < jend) {
         const int nst = (int)std::min<int64_t>(64, jend - j);
-        stage_block<F>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xs, Sx, ys, hs);
+        commit<F>(pf, A.T, m, j, xs, Sx, ys, hs);
+        const int64_t jn = j + nst;
+        if (jn < jend) prefetch<F>(pf, A.T, A.mu, A.df, A.dg, A.inv, jn);
+        const unsigned long long word = load_word(&A.alive[rbase >> 6]);
         unsigned long long colbits = 0ull;
         const bool full = (j - (i0 + R - 1)) >= m;
         if (full)
@@ -693,8 +749,8 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
 #pragma unroll
         for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(rm[q] > F(0)));
         ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, false);
-        j += nst;
-        go = sync_rows<Q>(A.alive, rbase, dm);
+        j = jn;
+        go = sync_rows_with<Q>(A.alive, rbase, word, dm);
     }
     evals += ev;
 }
@@ -713,7 +769,7 @@ __device__ __forceinline__ SweepArgs<float> args_of<float>(const SeriesDev& s, C
 {
     SweepArgs<float> A;
     A.T = s.T;
-    A.mu = s.mu;
+    A.mu = cur_mu(s, c);
     A.df = s.df32;
     A.dg = s.dg32;
     A.inv = s.inv32;
@@ -729,7 +785,7 @@ __device__ __forceinline__ SweepArgs<double> args_of<double>(const SeriesDev& s,
 {
     SweepArgs<double> A;
     A.T = s.T;
-    A.mu = s.mu;
+    A.mu = cur_mu(s, c);
     A.df = s.df64;
     A.dg = s.dg64;
     A.inv = s.inv64;
@@ -847,9 +903,13 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     unsigned long long ev = pair_count(i0, std::min<int64_t>(i0 + R, N), jbeg, 1, m, left);
     int64_t j = jbeg + 1;
     bool go = true;
+    Prefetch<double> pf;
+    if (j < jend) prefetch<double>(pf, A.T, A.mu, A.df, A.dg, A.inv, j);
     while (go && j < jend) {
         const int nst = (int)std::min<int64_t>(64, jend - j);
-        stage_block<double>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xs, Sx, ys, hs);
+        commit<double>(pf, A.T, m, j, xs, Sx, ys, hs);
+        if (j + nst < jend) prefetch<double>(pf, A.T, A.mu, A.df, A.dg, A.inv, j + nst);
+        const unsigned long long word = load_word(&A.alive[rbase >> 6]);
         bool full;
         if (left) full = (i0 - (j + nst - 1)) >= m;
         else full = (j - (i0 + R - 1)) >= m;
@@ -862,7 +922,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
 #pragma unroll
             for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(invi[q] > 0.0 && mx[q] * invi[q] > thr));
         }
-        go = sync_rows<Q>(A.alive, rbase, dm);
+        go = sync_rows_with<Q>(A.alive, rbase, word, dm);
     }
     // flat rows: correlation 1 with another flat window, 0 with any other
     const int64_t flo = c->flat_min, fhi = c->flat_max;
@@ -891,12 +951,12 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
 }
 
 // First selection pass: every row tile's nearest near_cols columns, split
-// into nsub chunks of `chunk` columns that run concurrently; each stops as
-// soon as the whole tile is dead.
+// into chunks of `chunk` columns that run concurrently; each stops as soon
+// as the whole tile is dead.
 template <typename F, int Q>
 __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
                                                     const int64_t* __restrict__ pfx, int near_cols,
-                                                    int chunk, int nsub)
+                                                    int chunk)
 {
     extern __shared__ double lds[];
     const int b = series_of(pfx, B, blockIdx.x);
@@ -906,10 +966,13 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
     constexpr int R = 64 * Q;
     const int64_t lb = blockIdx.x - pfx[b];
     const SweepArgs<F> A = args_of<F>(s, c);
-    const int64_t i0 = (lb / nsub) * R;
+    // chunk-major: every tile's nearest chunk is dispatched first, so later
+    // chunks find the rows their neighbours already pruned
+    const int64_t ntiles = (s.Nmax + R - 1) / R;
+    const int64_t i0 = (lb % ntiles) * R;
     if (i0 >= A.N) return;
     const int64_t j00 = i0 + A.m;
-    const int64_t jbeg = j00 + (lb % nsub) * chunk;
+    const int64_t jbeg = j00 + (lb / ntiles) * chunk;
     if (jbeg >= A.N || jbeg >= j00 + near_cols) return;
     const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
     const F thr = sel_threshold<F>(c);
@@ -977,8 +1040,15 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
     if (t >= ntiles) return;
     const int words = R / 64;
     unsigned long long any = 0ull;
-    for (int w = 0; w < words; ++w) any |= s.alive[t * words + w];
+    unsigned int cnt = 0;
+    for (int w = 0; w < words; ++w) {
+        const unsigned long long v = s.alive[t * words + w];
+        any |= v;
+        cnt += (unsigned int)__popcll(v);
+    }
     if (!any) return;
+    atomicAdd(mode == 0 ? &c->rows_near : &c->rows_far, (unsigned long long)cnt);
+    if (mode == 1) atomicAdd(&c->live_ref, cnt);
     const int64_t i0 = t * R;
     int64_t nch;
     if (mode == 0) {
@@ -1008,7 +1078,7 @@ __global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B, int chunk)
         const int b = (int)((blockIdx.x + (unsigned int)t) % (unsigned int)B);
         const SeriesDev& s = S[b];
         Ctrl* c = s.ctrl;
-        if (!c->active) continue;
+        if (!c->active || direct_round(c)) continue;
         const unsigned int nlive = c->nlive_ref;
         const unsigned long long total = (unsigned long long)nlive * c->maxc_ref;
         if (total == 0) continue;
@@ -1055,190 +1125,305 @@ __global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B, int chunk)
     }
 }
 
-// Survivor list: every row whose bit is still set.
-__global__ void k_survivors(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
-{
-    const int b = series_of(pfx, B, blockIdx.x);
-    const SeriesDev& s = S[b];
-    Ctrl* c = s.ctrl;
-    if (!c->active) return;
-    const int64_t w = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t N = s.n - c->m + 1;
-    if (w >= (N + 63) / 64) return;
-    unsigned long long bits = s.alive[w];
-    const int cnt = __popcll(bits);
-    if (!cnt) return;
-    unsigned int base = atomicAdd(&c->nsurv, (unsigned int)cnt);
-    while (bits) {
-        const int t = __ffsll((long long)bits) - 1;
-        s.surv[base++] = (int32_t)(w * 64 + t);
-        bits &= bits - 1ull;
-    }
-}
-
 struct Key {
     unsigned long long u;  // ordered bits of rho (ascending rho = descending nnDist)
     long long i;
 };
+constexpr long long KEY_NONE = 0x7fffffffffffffffll;
 __device__ __forceinline__ bool key_less(const Key& x, const Key& y)
 {
     return x.u < y.u || (x.u == y.u && x.i < y.i);
 }
-
-__global__ __launch_bounds__(TOPK_BLOCK) void k_topk(SeriesDev* S)
+__device__ __forceinline__ Key wave_min_key(Key k)
 {
-    __shared__ unsigned long long su[TOPK_BLOCK / 64];
-    __shared__ long long si[TOPK_BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        Key y;
+        y.u = __shfl_xor(k.u, o);
+        y.i = __shfl_xor(k.i, o);
+        if (key_less(y, k)) k = y;
+    }
+    return k;
+}
+
+// The round's range discords and the candidates to polish (one block per
+// series).  After a refinement sweep: count the subsequences still alive
+// (the range discords of this range search), pick the k + KP_EXTRA with the
+// smallest refined correlation (largest distance; ties: smaller index).  Each
+// wave first extracts the best of the bitmap words it owns by rounds of
+// wave-wide minimum (no block barriers), then wave 0 extracts the best of
+// the pooled per-wave lists.  In a direct round (no refinement sweep) every
+// live subsequence becomes a candidate.  Finally write the candidates'
+// centred windows x_k = t_{i+k} - mu_i and their sums for the exact pass.
+__global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
+{
+    constexpr int NW = TOPK_BLOCK / 64;
+    __shared__ unsigned long long pu[NW][KP_MAX];
+    __shared__ long long pi[NW][KP_MAX];
+    __shared__ unsigned int cnt_s[NW];
+    __shared__ long long cand_s[KP_MAX];
+    __shared__ unsigned int nc_s;
     const SeriesDev& s = S[blockIdx.x];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
-    const int k = s.k;
-    const unsigned int ns = c->nsurv;
-    if (ns < (unsigned int)k) {
-        if (threadIdx.x == 0) c->ncand = 0;
-        return;
-    }
-    const int32_t* __restrict__ surv = s.surv;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t m = c->m;
+    const int64_t N = s.n - m + 1;
+    const int64_t nw = (N + 63) / 64;
+    const unsigned long long* __restrict__ alive = s.alive;
     const unsigned long long* __restrict__ rho = s.rho;
-    const int kp = (int)min(ns, (unsigned int)(k + KP_EXTRA));
-    Key last = {0ull, -1};
-    bool have_last = false;
-    for (int r = 0; r < kp; ++r) {
-        Key best = {~0ull, 0x7fffffffffffffffll};
-        for (unsigned int q = threadIdx.x; q < ns; q += TOPK_BLOCK) {
-            const long long i = surv[q];
-            const Key x = {rho[i], i};
-            if (have_last && !key_less(last, x)) continue;
-            if (key_less(x, best)) best = x;
-        }
-        for (int o = 32; o >= 1; o >>= 1) {
-            Key y;
-            y.u = __shfl_xor(best.u, o);
-            y.i = __shfl_xor(best.i, o);
-            if (key_less(y, best)) best = y;
-        }
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
-            su[w] = best.u;
-            si[w] = best.i;
-        }
+    const int k = s.k;
+    int kp;
+    if (direct_round(c)) {
+        if (tid == 0) nc_s = 0;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            Key bb = {su[0], si[0]};
-            for (int q = 1; q < TOPK_BLOCK / 64; ++q) {
-                const Key y = {su[q], si[q]};
-                if (key_less(y, bb)) bb = y;
+        for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
+            unsigned long long bits = alive[q];
+            while (bits) {
+                const int t = __ffsll((long long)bits) - 1;
+                bits &= bits - 1ull;
+                const unsigned int slot = atomicAdd(&nc_s, 1u);
+                if (slot < (unsigned int)KP_MAX) cand_s[slot] = q * 64 + t;
             }
-            su[0] = bb.u;
-            si[0] = bb.i;
-            s.cand[r] = bb.i;
         }
         __syncthreads();
-        last.u = su[0];
-        last.i = si[0];
-        have_last = true;
+        kp = (int)min(nc_s, (unsigned int)KP_MAX);
+        if (kp < k) {
+            if (tid == 0) {
+                c->nsurv = (unsigned int)kp;
+                c->ncand = 0;
+            }
+            return;
+        }
+        if (tid < kp) s.cand[tid] = cand_s[tid];
+        if (tid == 0) {
+            c->nsurv = (unsigned int)kp;  // refined by k_round_end
+            c->ncand = (unsigned int)kp;
+        }
+    } else {
+        unsigned int cnt = 0;
+        for (int64_t q = tid; q < nw; q += TOPK_BLOCK) cnt += (unsigned int)__popcll(alive[q]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane == 0) cnt_s[w] = cnt;
         __syncthreads();
+        unsigned int ns = 0;
+        for (int q = 0; q < NW; ++q) ns += cnt_s[q];
+        if (ns < (unsigned int)k) {
+            if (tid == 0) {
+                c->nsurv = ns;
+                c->ncand = 0;
+            }
+            return;
+        }
+        kp = (int)min(ns, (unsigned int)(k + KP_EXTRA));
+        // per-wave best kp
+        {
+            Key last = {0ull, -1};
+            for (int r = 0; r < kp; ++r) {
+                Key best = {~0ull, KEY_NONE};
+                for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
+                    unsigned long long bits = alive[q];
+                    while (bits) {
+                        const int t = __ffsll((long long)bits) - 1;
+                        bits &= bits - 1ull;
+                        const long long i = q * 64 + t;
+                        const Key x = {rho[i], i};
+                        if (r > 0 && !key_less(last, x)) continue;
+                        if (key_less(x, best)) best = x;
+                    }
+                }
+                best = wave_min_key(best);
+                if (lane == 0) {
+                    pu[w][r] = best.u;
+                    pi[w][r] = best.i;
+                }
+                last = best;
+                if (__builtin_amdgcn_readfirstlane((int)(best.i == KEY_NONE))) {
+                    for (int q = r + 1 + lane; q < kp; q += 64) {
+                        pu[w][q] = ~0ull;
+                        pi[w][q] = KEY_NONE;
+                    }
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (w == 0) {
+            Key last = {0ull, -1};
+            for (int r = 0; r < kp; ++r) {
+                Key best = {~0ull, KEY_NONE};
+                for (int e = lane; e < NW * kp; e += 64) {
+                    const int ww = e / kp, rr = e - ww * kp;
+                    const Key x = {pu[ww][rr], pi[ww][rr]};
+                    if (x.i == KEY_NONE) continue;
+                    if (r > 0 && !key_less(last, x)) continue;
+                    if (key_less(x, best)) best = x;
+                }
+                best = wave_min_key(best);
+                if (lane == 0) {
+                    cand_s[r] = best.i;
+                    s.cand[r] = best.i;
+                }
+                last = best;
+            }
+        }
+        if (tid == 0) {
+            c->nsurv = ns;
+            c->ncand = (unsigned int)kp;
+        }
     }
-    if (threadIdx.x == 0) c->ncand = (unsigned int)kp;
+    __syncthreads();
+    const double* __restrict__ mu = cur_mu(s, c);
+    const int64_t stride = (int64_t)s.maxL + 8;
+    for (int r = w; r < kp; r += NW) {
+        const int64_t i = cand_s[r];
+        const double mui = mu[i];
+        double* x = s.xc + r * stride;
+        double sx = 0.0;
+        for (int kk = lane; kk < m; kk += 64) {
+            const double v = s.T[i + kk] - mui;
+            x[kk] = v;
+            sx += v;
+        }
+        sx = wave_sum(sx);
+        if (lane == 0) s.xc[KP_MAX * stride + r] = sx;
+    }
 }
 
 // Exact FP64 nearest-neighbour correlation of the candidate rows against
 // every column: direct centred dot products (no recurrence), the reference
-// the reported distances and neighbour indices come from.  A block owns 256
-// consecutive columns of one series, stages their windows in LDS once and
-// evaluates every candidate against them; it writes one (max rho, argmax j)
-// partial per candidate.
+// the reported distances and neighbour indices come from.  A block owns
+// POLISH_COLS consecutive columns of one series (POLISH_CPT per thread,
+// POLISH_BLOCK apart, so LDS reads are conflict free) for one group of
+// POLISH_G candidates (grid.y), and stages the columns' values in LDS.  The
+// candidates' centred windows pass through LDS in chunks of POLISH_KC, so
+// per window offset k a thread does POLISH_CPT + POLISH_G LDS reads (the
+// candidate values are broadcasts) for POLISH_G x POLISH_CPT FMAs.  One
+// (max rho, argmax j) partial per candidate.
+constexpr int POLISH_G = 4;
+constexpr int POLISH_KC = 256;
+
 __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
                                                          const int64_t* __restrict__ pfx)
 {
     extern __shared__ double lds[];
-    __shared__ double sh[16];
-    __shared__ double red_v[POLISH_BLOCK / 64];
-    __shared__ long long red_j[POLISH_BLOCK / 64];
+    __shared__ double red_v[POLISH_BLOCK / 64][POLISH_G];
+    __shared__ long long red_j[POLISH_BLOCK / 64][POLISH_G];
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
     const int ncand = (int)c->ncand;
-    if (ncand == 0) return;
+    if ((int)blockIdx.y * POLISH_G >= ncand) return;
     const int32_t m = c->m;
     const int64_t N = s.n - m + 1;
     const double* __restrict__ T = s.T;
-    const double* __restrict__ mu = s.mu;
-    const double* __restrict__ var = s.var;
-    double* ts = lds;                          // T[j0 .. j0 + 256 + m + 64)
-    double* xs = lds + POLISH_BLOCK + m + 64;  // centred candidate window, zero padded
+    const double* __restrict__ mu = cur_mu(s, c);
+    const double* __restrict__ var = cur_var(s, c);
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x - pfx[b];
-    const int64_t j0 = blk * POLISH_BLOCK;
-    for (int t = tid; t < POLISH_BLOCK + m + 64; t += POLISH_BLOCK) ts[t] = T[j0 + t];
-    const int64_t j = j0 + tid;
+    const int64_t j0 = blk * POLISH_COLS;
+    double* xg = lds;                          // [POLISH_G][POLISH_KC] candidate chunk
+    double* ts = lds + POLISH_G * POLISH_KC;   // T[j0 .. j0 + POLISH_COLS + m)
+    for (int t = tid; t < POLISH_COLS + m; t += POLISH_BLOCK) ts[t] = T[j0 + t];
     const double feps = c->flat_eps;
-    const bool colok = j < N;
-    const double sgj = colok ? sqrt(var[j]) : 1.0;
-    const double muj = colok ? mu[j] : 0.0;
-    const bool flat_j = colok && sgj <= feps;
+    int64_t jc[POLISH_CPT];
+    bool colok[POLISH_CPT], flat_j[POLISH_CPT];
+    double sgj[POLISH_CPT], muj[POLISH_CPT];
+#pragma unroll
+    for (int q = 0; q < POLISH_CPT; ++q) {
+        jc[q] = j0 + tid + q * POLISH_BLOCK;
+        colok[q] = jc[q] < N;
+        sgj[q] = colok[q] ? sqrt(var[jc[q]]) : 1.0;
+        muj[q] = colok[q] ? mu[jc[q]] : 0.0;
+        flat_j[q] = colok[q] && sgj[q] <= feps;
+    }
+    const int64_t stride = (int64_t)s.maxL + 8;
+    const double* __restrict__ xc = s.xc;
+    const int w = tid >> 6;
     unsigned long long ev = 0;
-    for (int cid = 0; cid < ncand; ++cid) {
-        const int64_t i = s.cand[cid];
-        const double mui = mu[i];
-        double sx = 0.0;
-        __syncthreads();  // previous candidate's xs fully consumed
-        for (int k = tid; k < m + 64; k += POLISH_BLOCK) {
-            const double x = k < m ? T[i + k] - mui : 0.0;
-            xs[k] = x;
-            sx += x;
-        }
-        const double s0 = block_sum(sx, sh);
-        if (tid == 0) sh[15] = s0;
-        __syncthreads();
-        const double Sx = sh[15];
-        const double sgi = sqrt(var[i]);
-        const bool flat_i = sgi <= feps;
-        double best = -f_inf<double>();
-        long long bj = 0x7fffffffffffffffll;
-        if (colok && (j <= i - m || j >= i + m)) {
-            double rh;
-            if (flat_i || flat_j) {
-                rh = (flat_i && flat_j) ? 1.0 : 0.0;
-            } else {
-                const double* t = ts + tid;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                for (int k = 0; k < m; k += 4) {
-                    a0 = fma(xs[k], t[k], a0);
-                    a1 = fma(xs[k + 1], t[k + 1], a1);
-                    a2 = fma(xs[k + 2], t[k + 2], a2);
-                    a3 = fma(xs[k + 3], t[k + 3], a3);
+    {
+        const int g0 = (int)blockIdx.y * POLISH_G;
+        int cidx[POLISH_G];
+#pragma unroll
+        for (int g = 0; g < POLISH_G; ++g) cidx[g] = min(g0 + g, ncand - 1);
+        double acc[POLISH_G][POLISH_CPT];
+#pragma unroll
+        for (int g = 0; g < POLISH_G; ++g)
+#pragma unroll
+            for (int q = 0; q < POLISH_CPT; ++q) acc[g][q] = 0.0;
+        for (int kb = 0; kb < m; kb += POLISH_KC) {
+            const int kn = min(POLISH_KC, m - kb);
+            __syncthreads();  // the previous chunk (and ts) complete / consumed
+            for (int e = tid; e < POLISH_G * POLISH_KC; e += POLISH_BLOCK) {
+                const int g = e / POLISH_KC, k = e - g * POLISH_KC;
+                xg[e] = k < kn ? xc[cidx[g] * stride + kb + k] : 0.0;
+            }
+            __syncthreads();
+            const double* tb = ts + tid + kb;
+#pragma unroll 2
+            for (int k = 0; k < kn; ++k) {
+                double tv[POLISH_CPT];
+#pragma unroll
+                for (int q = 0; q < POLISH_CPT; ++q) tv[q] = tb[q * POLISH_BLOCK + k];
+#pragma unroll
+                for (int g = 0; g < POLISH_G; ++g) {
+                    const double x = xg[g * POLISH_KC + k];
+#pragma unroll
+                    for (int q = 0; q < POLISH_CPT; ++q) acc[g][q] = fma(x, tv[q], acc[g][q]);
                 }
-                const double Cv = (a0 + a1) + (a2 + a3) - muj * Sx;
-                rh = Cv / ((double)m * sgi * sgj);
-                rh = fmin(1.0, fmax(-1.0, rh));
-            }
-            best = rh;
-            bj = j;
-            ++ev;
-        }
-        for (int o = 32; o >= 1; o >>= 1) {
-            const double v = __shfl_xor(best, o);
-            const long long jj = __shfl_xor(bj, o);
-            if (v > best || (v == best && jj < bj)) {
-                best = v;
-                bj = jj;
             }
         }
-        const int w = tid >> 6;
-        if ((tid & 63) == 0) {
-            red_v[w] = best;
-            red_j[w] = bj;
+#pragma unroll
+        for (int g = 0; g < POLISH_G; ++g) {
+            const int64_t i = s.cand[cidx[g]];
+            const double Sx = xc[KP_MAX * stride + cidx[g]];
+            const double sgi = sqrt(var[i]);
+            const bool flat_i = sgi <= feps;
+            double best = -f_inf<double>();
+            long long bj = 0x7fffffffffffffffll;
+#pragma unroll
+            for (int q = 0; q < POLISH_CPT; ++q) {
+                if (colok[q] && (jc[q] <= i - m || jc[q] >= i + m)) {
+                    double rh;
+                    if (flat_i || flat_j[q]) {
+                        rh = (flat_i && flat_j[q]) ? 1.0 : 0.0;
+                    } else {
+                        const double Cv = acc[g][q] - muj[q] * Sx;
+                        rh = fmin(1.0, fmax(-1.0, Cv / ((double)m * sgi * sgj[q])));
+                    }
+                    if (rh > best) {  // columns ascend with q: ties keep the smaller j
+                        best = rh;
+                        bj = jc[q];
+                    }
+                    if (g0 + g < ncand) ++ev;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double v = __shfl_xor(best, o);
+                const long long jj = __shfl_xor(bj, o);
+                if (v > best || (v == best && jj < bj)) {
+                    best = v;
+                    bj = jj;
+                }
+            }
+            if ((tid & 63) == 0) {
+                red_v[w][g] = best;
+                red_j[w][g] = bj;
+            }
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid < POLISH_G && g0 + tid < ncand) {
+            double best = red_v[0][tid];
+            long long bj = red_j[0][tid];
             for (int q = 1; q < POLISH_BLOCK / 64; ++q)
-                if (red_v[q] > best || (red_v[q] == best && red_j[q] < bj)) {
-                    best = red_v[q];
-                    bj = red_j[q];
+                if (red_v[q][tid] > best || (red_v[q][tid] == best && red_j[q][tid] < bj)) {
+                    best = red_v[q][tid];
+                    bj = red_j[q][tid];
                 }
-            const int64_t slot = ((int64_t)cid * s.npart + blk) * 2;
+            const int64_t slot = ((int64_t)(g0 + tid) * s.npart + blk) * 2;
             s.part[slot] = best;
             s.part[slot + 1] = (double)bj;
         }
@@ -1247,59 +1432,11 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
     if ((tid & 63) == 0 && ev) atomicAdd(&c->evals_pol, ev);
 }
 
-// Reduce the polish partials of each candidate to (rho, j) in part's tail.
-// grid: (KP_MAX, B).
-__global__ void k_polish_reduce(SeriesDev* S)
-{
-    __shared__ double rv[4];
-    __shared__ double rj[4];
-    const SeriesDev& s = S[blockIdx.y];
-    Ctrl* c = s.ctrl;
-    if (!c->active) return;
-    const int cid = blockIdx.x;
-    if ((unsigned int)cid >= c->ncand) return;
-    const int64_t npart = s.npart;
-    const int32_t m = c->m;
-    const int64_t nblk = (s.n - m + 1 + POLISH_BLOCK - 1) / POLISH_BLOCK;
-    double best = -f_inf<double>(), bj = 1e300;
-    for (int64_t p = threadIdx.x; p < nblk; p += blockDim.x) {
-        const double v = s.part[((int64_t)cid * npart + p) * 2];
-        const double jj = s.part[((int64_t)cid * npart + p) * 2 + 1];
-        if (v > best || (v == best && jj < bj)) {
-            best = v;
-            bj = jj;
-        }
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        const double v = __shfl_xor(best, o);
-        const double jj = __shfl_xor(bj, o);
-        if (v > best || (v == best && jj < bj)) {
-            best = v;
-            bj = jj;
-        }
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        rv[w] = best;
-        rj[w] = bj;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
-            if (rv[q] > best || (rv[q] == best && rj[q] < bj)) {
-                best = rv[q];
-                bj = rj[q];
-            }
-        const int64_t tail = (int64_t)KP_MAX * npart * 2;
-        s.part[tail + cid * 2] = best;
-        s.part[tail + cid * 2 + 1] = bj;
-    }
-}
-
-// Rank the polished candidates, write the length's top-k rows when the round
-// found at least k range discords, and advance MERLIN's r otherwise.
-// grid: B blocks of 128 threads.
-__global__ void k_round_end(SeriesDev* S)
+// Close the round of every series (one block each): reduce the polish
+// partials to each candidate's exact (rho, j), rank the candidates, write the
+// length's top-k rows when the round found at least k range discords, and
+// lower MERLIN's r otherwise; count the series with work left in rem[0].
+__global__ __launch_bounds__(256) void k_round_end(SeriesDev* S, int32_t* rem)
 {
     __shared__ double nn_s[KP_MAX];
     __shared__ long long id_s[KP_MAX];
@@ -1307,40 +1444,84 @@ __global__ void k_round_end(SeriesDev* S)
     const SeriesDev& s = S[blockIdx.x];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
+    __shared__ int valid_s[KP_MAX];
+    __shared__ unsigned int nvalid_s;
     const int k = s.k;
     const int32_t m = c->m;
     const int li = c->li;
-    const unsigned int ns = c->nsurv;
     const int kp = (int)c->ncand;
-    const bool ok = ns >= (unsigned int)k && kp >= k;
-    const int64_t tail = (int64_t)KP_MAX * s.npart * 2;
-    const int t = threadIdx.x;
-    if (ok && t < kp) {
-        const double rho = s.part[tail + t * 2];
-        const double d2 = 2.0 * (double)m * (1.0 - rho);
-        nn_s[t] = sqrt(fmin(4.0 * (double)m, fmax(0.0, d2)));
-        id_s[t] = s.cand[t];
-        jj_s[t] = (long long)s.part[tail + t * 2 + 1];
-    }
-    __syncthreads();
-    if (ok && t < kp) {
-        int rank = 0;
-        for (int q = 0; q < kp; ++q)
-            if (nn_s[q] > nn_s[t] || (nn_s[q] == nn_s[t] && id_s[q] < id_s[t])) ++rank;
-        if (rank < k) {
-            const int64_t row = (int64_t)li * k + rank;
-            if (s.idx) {
-                s.idx[row] = id_s[t];
-                s.len[row] = m;
-                s.nn[row] = nn_s[t];
-                s.nnidx[row] = jj_s[t];
+    const bool direct = direct_round(c);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (kp >= k) {
+        const int64_t npart = s.npart;
+        const int64_t nblk = (s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS;
+        for (int cid = w; cid < kp; cid += 4) {
+            double best = -f_inf<double>(), bj = 1e300;
+            for (int64_t p = lane; p < nblk; p += 64) {
+                const double v = s.part[((int64_t)cid * npart + p) * 2];
+                const double jj = s.part[((int64_t)cid * npart + p) * 2 + 1];
+                if (v > best || (v == best && jj < bj)) {
+                    best = v;
+                    bj = jj;
+                }
             }
-            if (rank == k - 1) s.hist[li] = nn_s[t];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double v = __shfl_xor(best, o);
+                const double jj = __shfl_xor(bj, o);
+                if (v > best || (v == best && jj < bj)) {
+                    best = v;
+                    bj = jj;
+                }
+            }
+            if (lane == 0) {
+                const double d2 = 2.0 * (double)m * (1.0 - best);
+                const long long i = s.cand[cid];
+                nn_s[cid] = sqrt(fmin(4.0 * (double)m, fmax(0.0, d2)));
+                id_s[cid] = i;
+                jj_s[cid] = (long long)bj;
+                // a direct round decides here which live subsequences are range
+                // discords (distance >= r, i.e. rho <= thr64), as refinement would
+                int ok_i = 1;
+                if (direct) {
+                    ok_i = !(c->prune && best > c->thr64);
+                    if (ok_i) s.rho[i] = ord_of(best);
+                    else atomicAnd(&s.alive[i >> 6], ~(1ull << (i & 63)));
+                }
+                valid_s[cid] = ok_i;
+            }
         }
     }
     __syncthreads();
-    if (t == 0) {
+    if (tid == 0) {
+        unsigned int nv = 0;
+        for (int q = 0; q < kp; ++q) nv += (unsigned int)valid_s[q];
+        nvalid_s = nv;
+    }
+    __syncthreads();
+    const unsigned int ns = direct ? (kp >= k ? nvalid_s : (unsigned int)kp) : c->nsurv;
+    const bool ok = ns >= (unsigned int)k && kp >= k;
+    if (ok && tid < kp && valid_s[tid]) {
+        int rank = 0;
+        for (int q = 0; q < kp; ++q)
+            if (valid_s[q] &&
+                (nn_s[q] > nn_s[tid] || (nn_s[q] == nn_s[tid] && id_s[q] < id_s[tid])))
+                ++rank;
+        if (rank < k) {
+            const int64_t row = (int64_t)li * k + rank;
+            if (s.idx) {
+                s.idx[row] = id_s[tid];
+                s.len[row] = m;
+                s.nn[row] = nn_s[tid];
+                s.nnidx[row] = jj_s[tid];
+            }
+            if (rank == k - 1) s.hist[li] = nn_s[tid];
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
         c->rounds += 1;
+        c->nsurv = ns;
         if (ok) {
             c->done = 1;
             c->survivors += ns;
@@ -1351,28 +1532,7 @@ __global__ void k_round_end(SeriesDev* S)
             else if (c->mode == 1) c->r *= 0.99;
             else if (c->mode == 2) c->r = (c->step > 0.0) ? c->r - c->step : 0.99 * c->r;
         }
-    }
-}
-
-// Series with work left after this round (one block).
-__global__ void k_remaining(SeriesDev* S, int B, int32_t* out)
-{
-    __shared__ int cnt[2];
-    if (threadIdx.x == 0) {
-        cnt[0] = 0;
-        cnt[1] = 0;
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < B; b += blockDim.x) {
-        const Ctrl* c = S[b].ctrl;
-        const bool left = !c->finished && !(c->started && c->done && c->m >= S[b].maxL);
-        if (left) atomicAdd(&cnt[0], 1);
-        if (c->error) atomicAdd(&cnt[1], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        out[0] = cnt[0];
-        out[1] = cnt[1];
+        if (!(c->done && c->m >= s.maxL)) atomicAdd(&rem[0], 1);
     }
 }
 
@@ -1383,11 +1543,10 @@ template <typename F, int Q>
 static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
     const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
-    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
     if (total[PFX_NEAR] == 0) return;
     cfg.timer->begin(0, st);
     hipLaunchKernelGGL((k_select_near<F, Q>), dim3((unsigned int)total[PFX_NEAR]), dim3(64), lds,
-                       st, bt.s, bt.B, bt.pfx[PFX_NEAR], cfg.near_cols, cfg.chunk_cols, nsub);
+                       st, bt.s, bt.B, bt.pfx[PFX_NEAR], cfg.near_cols, cfg.chunk_cols);
     cfg.timer->end(0, st);
 }
 
@@ -1424,6 +1583,12 @@ static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* t
     case 4: launch_near<F, 4>(bt, cfg, total, st); break;
     default: launch_near<F, 8>(bt, cfg, total, st); break;
     }
+    if ((int64_t)cfg.near_cols >= bt.Nmax_all) {
+        // the first pass already covers every column of every series
+        cfg.timer->begin(1, st);
+        cfg.timer->end(1, st);
+        return;
+    }
     switch (cfg.q_far) {
     case 2: launch_far<F, 2>(bt, cfg, total, st); break;
     case 4: launch_far<F, 4>(bt, cfg, total, st); break;
@@ -1436,11 +1601,9 @@ static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* t
 hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
     const unsigned int elem = (unsigned int)total[PFX_ELEM];
-    hipLaunchKernelGGL(k_round_prep, dim3((bt.B + 63) / 64), dim3(64), 0, st, bt.s, bt.B);
-    hipLaunchKernelGGL(k_stats, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
-    hipLaunchKernelGGL(k_helpers, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
-    hipLaunchKernelGGL(k_round_begin, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM],
-                       cfg.guard);
+    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(256), 0, st, bt.s, bt.B, cfg.guard,
+                       bt.remaining);
+    hipLaunchKernelGGL(k_length, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
     if (cfg.dist_bits == 64) launch_select<double>(bt, cfg, total, st);
     else launch_select<float>(bt, cfg, total, st);
     switch (cfg.q_ref) {
@@ -1448,17 +1611,14 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
     case 8: launch_refine<8>(bt, cfg, total, st); break;
     default: launch_refine<2>(bt, cfg, total, st); break;
     }
-    hipLaunchKernelGGL(k_survivors, dim3((unsigned int)total[PFX_WORDS]), dim3(256), 0, st, bt.s,
-                       bt.B, bt.pfx[PFX_WORDS]);
-    hipLaunchKernelGGL(k_topk, dim3(bt.B), dim3(TOPK_BLOCK), 0, st, bt.s);
-    const size_t lds = sizeof(double) * (size_t)(POLISH_BLOCK + 2 * (bt.maxL_all + 64));
+    hipLaunchKernelGGL(k_select_top, dim3(bt.B), dim3(TOPK_BLOCK), 0, st, bt.s);
+    const size_t lds = sizeof(double) * (size_t)(POLISH_G * POLISH_KC + POLISH_COLS + bt.maxL_all);
     cfg.timer->begin(3, st);
-    hipLaunchKernelGGL(k_polish, dim3((unsigned int)total[PFX_POLISH]), dim3(POLISH_BLOCK), lds, st,
-                       bt.s, bt.B, bt.pfx[PFX_POLISH]);
+    hipLaunchKernelGGL(k_polish,
+                       dim3((unsigned int)total[PFX_POLISH], (KP_MAX + POLISH_G - 1) / POLISH_G),
+                       dim3(POLISH_BLOCK), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
     cfg.timer->end(3, st);
-    hipLaunchKernelGGL(k_polish_reduce, dim3(KP_MAX, bt.B), dim3(256), 0, st, bt.s);
-    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(128), 0, st, bt.s);
-    hipLaunchKernelGGL(k_remaining, dim3(1), dim3(256), 0, st, bt.s, bt.B, bt.remaining);
+    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(256), 0, st, bt.s, bt.remaining);
     return hipGetLastError();
 }
 
@@ -1477,10 +1637,16 @@ hipError_t launch_set_fixed_r(const Batch& bt, double r, hipStream_t st)
 
 __global__ void k_set_len(SeriesDev* S, int32_t m, int32_t new_len)
 {
-    Ctrl* c = S[0].ctrl;
+    const SeriesDev& s = S[0];
+    Ctrl* c = s.ctrl;
     c->m = m;
+    c->li = m - s.minL;
     c->new_len = new_len;
     c->active = 1;
+    if (new_len) {
+        c->flat_min = 0x7fffffffffffffffll;
+        c->flat_max = -1;
+    }
 }
 
 hipError_t launch_set_len(const Batch& bt, int32_t m, hipStream_t st)
@@ -1495,18 +1661,19 @@ hipError_t launch_stats_to(const Batch& bt, int32_t minL, int32_t m, const int64
 {
     for (int32_t mm = minL; mm <= m; ++mm) {
         hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, mm, mm == minL ? 2 : 1);
-        hipLaunchKernelGGL(k_stats, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
+        hipLaunchKernelGGL(k_length, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
                            bt.pfx[PFX_ELEM]);
     }
     return hipGetLastError();
 }
 
 // Sum of the per-series counters of a call (one block):
-// out = {evals_sel, evals_ref, evals_pol, rounds, survivors, evals_near, evals_far}.
+// out = {evals_sel, evals_ref, evals_pol, rounds, survivors, evals_near, evals_far,
+//        rows_near, rows_far}.
 __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
 {
-    __shared__ unsigned long long acc[7];
-    if (threadIdx.x < 7) acc[threadIdx.x] = 0ull;
+    __shared__ unsigned long long acc[9];
+    if (threadIdx.x < 9) acc[threadIdx.x] = 0ull;
     __syncthreads();
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         const Ctrl* c = S[b].ctrl;
@@ -1517,9 +1684,11 @@ __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
         atomicAdd(&acc[4], c->survivors);
         atomicAdd(&acc[5], c->evals_near);
         atomicAdd(&acc[6], c->evals_far);
+        atomicAdd(&acc[7], c->rows_near);
+        atomicAdd(&acc[8], c->rows_far);
     }
     __syncthreads();
-    if (threadIdx.x < 7) out[threadIdx.x] = acc[threadIdx.x];
+    if (threadIdx.x < 9) out[threadIdx.x] = acc[threadIdx.x];
 }
 
 hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_t st)
@@ -1557,8 +1726,8 @@ __global__ void k_stats_out(SeriesDev* S, int64_t N, double* mo, double* so)
     const SeriesDev& s = S[0];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    mo[i] = s.mu[i];
-    so[i] = sqrt(s.var[i]);
+    mo[i] = cur_mu(s, s.ctrl)[i];
+    so[i] = sqrt(cur_var(s, s.ctrl)[i]);
 }
 
 hipError_t launch_stats_out(const Batch& bt, int64_t N, double* mu, double* sigma, hipStream_t st)
@@ -1586,21 +1755,23 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.Npad = ((l.Nmax + 1 + R_MAX - 1) / R_MAX) * R_MAX + R_MAX;
     l.Tlen = l.Npad + maxL + 256;
     l.nwords = l.Npad / 64 + 1;
-    l.npart = (l.Nmax + POLISH_BLOCK - 1) / POLISH_BLOCK;
+    l.npart = (l.Nmax + POLISH_COLS - 1) / POLISH_COLS;
     const size_t hl = (size_t)(l.Npad + 64);
     size_t o = 0;
     l.off_T = o;     o = al256(o + sizeof(double) * (size_t)l.Tlen);
     l.off_mu = o;    o = al256(o + sizeof(double) * hl);
     l.off_var = o;   o = al256(o + sizeof(double) * hl);
+    l.off_mu2 = o;   o = al256(o + sizeof(double) * hl);
+    l.off_var2 = o;  o = al256(o + sizeof(double) * hl);
     l.off_h32 = o;   o = al256(o + 3 * al256(sizeof(float) * hl));
     l.off_h64 = o;   o = al256(o + 3 * al256(sizeof(double) * hl));
     l.off_alive = o; o = al256(o + sizeof(unsigned long long) * (size_t)l.nwords);
     l.off_rho = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
     l.off_tsel = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_tref = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
-    l.off_surv = o;  o = al256(o + sizeof(int32_t) * (size_t)l.Npad);
     l.off_cand = o;  o = al256(o + sizeof(int64_t) * (size_t)KP_MAX);
     l.off_part = o;  o = al256(o + sizeof(double) * (size_t)(2 * KP_MAX * (l.npart + 1)));
+    l.off_xc = o;    o = al256(o + sizeof(double) * (size_t)KP_MAX * (size_t)(maxL + 9));
     l.off_hist = o;  o = al256(o + sizeof(double) * (size_t)(l.L > 0 ? l.L : 1));
     l.off_ctrl = o;  o = al256(o + sizeof(Ctrl));
     l.off_red = o;   o = al256(o + sizeof(double) * 2 * RED_BLOCKS);
@@ -1628,6 +1799,8 @@ SeriesDev carve(void* base, const Layout& l)
     s.T = (double*)(p + l.off_T);
     s.mu = (double*)(p + l.off_mu);
     s.var = (double*)(p + l.off_var);
+    s.mu2 = (double*)(p + l.off_mu2);
+    s.var2 = (double*)(p + l.off_var2);
     s.df32 = (float*)(p + l.off_h32);
     s.dg32 = (float*)(p + l.off_h32 + al256(sizeof(float) * hl));
     s.inv32 = (float*)(p + l.off_h32 + 2 * al256(sizeof(float) * hl));
@@ -1638,9 +1811,9 @@ SeriesDev carve(void* base, const Layout& l)
     s.rho = (unsigned long long*)(p + l.off_rho);
     s.tsel = (int32_t*)(p + l.off_tsel);
     s.tref = (int32_t*)(p + l.off_tref);
-    s.surv = (int32_t*)(p + l.off_surv);
     s.cand = (int64_t*)(p + l.off_cand);
     s.part = (double*)(p + l.off_part);
+    s.xc = (double*)(p + l.off_xc);
     s.hist = (double*)(p + l.off_hist);
     s.ctrl = (Ctrl*)(p + l.off_ctrl);
     s.red = (double*)(p + l.off_red);
@@ -1650,12 +1823,13 @@ SeriesDev carve(void* base, const Layout& l)
 void series_blocks(const Layout& l, const SweepCfg& cfg, int64_t out[PFX_KINDS])
 {
     const int rn = 64 * cfg.q_near, rf = 64 * cfg.q_far, rr = 64 * cfg.q_ref;
-    const int nsub = (cfg.near_cols + cfg.chunk_cols - 1) / cfg.chunk_cols;
+    // chunks of the first pass: near_cols, at most every column
+    const int64_t span = std::min<int64_t>((int64_t)cfg.near_cols, l.Nmax);
+    const int64_t nsub = (span + cfg.chunk_cols - 1) / cfg.chunk_cols;
     out[PFX_ELEM] = (l.Npad + 64 + 255) / 256;
     out[PFX_NEAR] = ((l.Nmax + rn - 1) / rn) * nsub;
     out[PFX_TSEL] = ((l.Nmax + rf - 1) / rf + 255) / 256;
     out[PFX_TREF] = ((l.Nmax + rr - 1) / rr + 255) / 256;
-    out[PFX_WORDS] = (l.nwords + 255) / 256;
     out[PFX_POLISH] = l.npart;
 }
 

@@ -89,6 +89,8 @@ def test_batched_graph_replay_and_direct_launch_agree():
             assert torch.equal(a[s][key], d[s][key]), (s, key)
     assert st["range_searches"] >= sum(h - l + 1 for l, h in zip(lo, hi))
     assert st["kernel_launches"][0] > 0
+    # every range discord was live when refinement started
+    assert st["rows_after_far"] >= st["survivors"] >= sum(h - l + 1 for l, h in zip(lo, hi)) * 3
 
 
 def test_batched_single_series_equals_plain():

@@ -177,6 +177,22 @@ def test_config2_matches_golden():
     _match_golden(w.T, out, g)
 
 
+def test_config5_matches_golden():
+    """Random walk n=200,000 with ten sine bursts, m 96..160, top-5 (the
+    gradient workload's forward pass) against the oracle's stored output."""
+    g = _golden("c5")
+    if g is None:
+        pytest.skip("config-5 golden not generated")
+    dev = _dev()
+    api = _api()
+    w = synth.config5()
+    assert synth.sha256(w.T) == g["sha256"]
+    _say("config5")
+    out = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, w.k)
+    _match_golden(w.T, out, g)
+    np.testing.assert_array_equal(out["len"].cpu().numpy(), np.array(g["len"]))
+
+
 def test_edge_cases():
     dev = _dev()
     api = _api()
