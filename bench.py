@@ -65,7 +65,7 @@ def cpu_baseline(w, golden, n_lengths: int):
     }
 
 
-def batched_vs_plain(api, synth, torch, dev, reps: int, tune: bool):
+def batched_vs_plain(api, synth, tuning, torch, dev, reps: int, retune: bool):
     """64 uneven series (lengths log-uniform in [1e4, 2e5], each with its own
     length range of 51 lengths, top-1): one batched call against a loop of
     single-series calls over the same series.  The batched call uses tile
@@ -81,9 +81,10 @@ def batched_vs_plain(api, synth, torch, dev, reps: int, tune: bool):
     wsb = torch.empty(nb, dtype=torch.uint8, device=dev)
     flat = torch.cat(vals)
     sizes = [v.shape[0] for v in vals]
-    tuned, report = ({}, None)
-    if tune:
-        tuned, report = api.autotune(vals, lo, hi, 1, probe_lengths=6, reps=1)
+    tuned, report = tuning.options(tuning.BATCH_NAME), "stored"
+    if retune:
+        probe, treps = tuning.PROBES["batch"]
+        tuned, report = api.autotune(vals, lo, hi, 1, probe_lengths=probe, reps=treps)
     res = api.discords_batched((flat, sizes), lo, hi, 1, workspace=wsb, **tuned)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -113,7 +114,7 @@ def batched_vs_plain(api, synth, torch, dev, reps: int, tune: bool):
                for key in ("idx", "len", "nn_dist", "nn_idx", "count"))
     t_plain = min(plain.values())
     return {
-        "workload": "batch64_rw+ecg_n1e4-2e5_m(50..100)+50_k1_fp32",
+        "workload": tuning.BATCH_NAME,
         "series": len(ws),
         "points": int(sum(sizes)),
         "lengths": lengths,
@@ -129,6 +130,23 @@ def batched_vs_plain(api, synth, torch, dev, reps: int, tune: bool):
         "tune_report": report,
         "reps": reps,
     }
+
+
+def measured_traffic(kernel: str, workload: str, options: dict):
+    """HBM bytes per launch of `kernel` from the stored hardware-counter
+    summary under profiles/, if it was taken on this exact kernel source,
+    workload and tile geometry (None otherwise)."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2304_01660_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        rec = json.load(open(path))
+        if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                and rec.get("tile_options") == options and rec.get("kernels_hip_sha256") == sha):
+            return rec["bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
 
 
 def check_golden(out, golden, T):
@@ -152,9 +170,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-lengths", type=int, default=6)
+    ap.add_argument("--cpu-lengths", type=int, default=12)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one plain device-to-device copy of MIB MiB (a known-size "
+                         "reference for hardware traffic counters) and exit")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner now instead of using the stored tile options")
     ap.add_argument("--batch-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -164,19 +186,28 @@ def main():
 
     import torch
 
-    from paper_2304_01660_amd import api, synth
+    from paper_2304_01660_amd import api, synth, tuning
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe * 2**20 // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8}), flush=True)
+        return 0
     w = synth.config2()
     L = w.maxL - w.minL + 1
     gpath = os.path.join(ROOT, "tests", "golden", "c2_rw100k_m64-128_k3_fp32.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     T = torch.from_numpy(w.T).to(dev)
     ws = torch.empty(api.workspace_size(w.n, w.minL, w.maxL, w.k), dtype=torch.uint8, device=dev)
-    # tile geometry from the autotuner (probing the first lengths), untimed
-    tuned, tune_report = ({}, None)
-    if not args.no_tune:
-        tuned, tune_report = api.autotune(T, w.minL, w.maxL, w.k, probe_lengths=8, reps=1)
+    # tile geometry chosen by the autotuner (stored, or tuned now, untimed)
+    tuned, tune_report = tuning.options(w.name), "stored"
+    if args.retune:
+        probe, treps = tuning.PROBES["single"]
+        tuned, tune_report = api.autotune(T, w.minL, w.maxL, w.k, probe_lengths=probe, reps=treps)
     for _ in range(args.warmup):
         api.discords(T, w.minL, w.maxL, w.k, workspace=ws, **tuned)
     torch.cuda.synchronize()
@@ -232,13 +263,16 @@ def main():
     if dk["ms_per_step"] > 0:
         # evals per launch / average launch duration == evals / summed duration
         achieved = dk["evals_per_step"] * OPS_PER_EVAL / (dk["ms_per_step"] * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic(KERNEL_NAMES[dom], w.name, tuned)
     roofline = {
         "bound": "alu",
         "achieved": achieved,
         "peak": VALU_PEAK_TOPS,
         "unit": "Top/s",
         "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (HBM, counter-measured)",
+        "traffic_source": traffic_src,
         "kernel": KERNEL_NAMES[dom],
         "ops_per_eval": OPS_PER_EVAL,
         "avg_launch_us": dk["avg_launch_us"],
@@ -247,7 +281,7 @@ def main():
     }
     batched = None
     if not args.no_batched:
-        batched = batched_vs_plain(api, synth, torch, dev, args.batch_reps, not args.no_tune)
+        batched = batched_vs_plain(api, synth, tuning, torch, dev, args.batch_reps, args.retune)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_lengths)
