@@ -11,7 +11,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpalmad.so")
+# PALMAD_LIBRARY may point at another build of the same library (profiling
+# builds); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("PALMAD_LIBRARY") or os.path.join(_HERE, "libpalmad.so")
 
 PALMAD_OK = 0
 STATUS = {

@@ -383,55 +383,81 @@ struct SweepArgs {
     int32_t m;
 };
 
-// Stage the centred windows of the tile's first row (xs, for the top
-// boundary) and of the first column (ys, for the initial column) in LDS,
-// zero padded by 64, and return their sums (zero up to rounding).
-__device__ __forceinline__ void stage_windows(const double* __restrict__ T,
-                                              const double* __restrict__ mu, int32_t m, int64_t i0,
-                                              int64_t jbeg, double* xs, double* ys, double& Sx,
-                                              double& Sy)
+// Copy count doubles from global memory to LDS (the whole workgroup): groups
+// of eight loads per thread are issued before their stores, so one memory
+// latency covers 8 x blockDim values.
+__device__ __forceinline__ void lds_fill(double* dst, const double* __restrict__ src, int count)
 {
-    const int lane = threadIdx.x;
-    const double mui = mu[i0], muj = mu[jbeg];
-    double sx = 0.0, sy = 0.0;
-    for (int k = lane; k < m + 64; k += 64) {
-        double x = 0.0, y = 0.0;
-        if (k < m) {
-            x = T[i0 + k] - mui;
-            y = T[jbeg + k] - muj;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int base = 0; base < count; base += nt * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = base + tid + nt * u;
+            v[u] = t < count ? src[t] : 0.0;
         }
-        xs[k] = x;
-        ys[k] = y;
-        sx += x;
-        sy += y;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = base + tid + nt * u;
+            if (t < count) dst[t] = v[u];
+        }
     }
-    Sx = wave_sum(sx);
-    Sy = wave_sum(sy);
-    __syncthreads();
 }
 
-// C(rbase+q, jbeg) for the lane's Q rows: sum_k t_{i+k} y_k - mu_i * Sy.
+// Start of a sweep work item (one wavefront, row tile of R = 64 Q rows from
+// i0, first column jbeg):
+//  * acc[q] = C(rbase + q, jbeg), rbase = i0 + Q lane: centred dot products
+//    sum_k t_{i+k} y_k - mu_i Sy with y the centred window of column jbeg.
+//    The rows' windows are staged in LDS (area: R + m values) and evaluated
+//    with lane l taking rows l, l + 64, ... (conflict-free LDS reads), then
+//    transposed through LDS to the lane's contiguous rows;
+//  * area then holds xs, the centred window of the tile's top row zero padded
+//    by 64, with sum Sx (zero up to rounding), for the top-boundary values.
+// win must hold max(m + 64, R) values.
 template <int Q>
-__device__ __forceinline__ void initial_column(const double* __restrict__ T,
-                                               const double* __restrict__ mu, int32_t m,
-                                               int64_t rbase, const double* ys, double Sy,
-                                               double (&acc)[Q])
+__device__ void item_start(const double* __restrict__ T, const double* __restrict__ mu, int32_t m,
+                           int64_t i0, int64_t jbeg, double* area, double* win, double& Sx,
+                           double& Sy, double (&acc)[Q])
 {
+    constexpr int R = 64 * Q;
+    const int lane = threadIdx.x;
+    lds_fill(area, T + i0, R + m);
+    lds_fill(win, T + jbeg, m);
+    const double muj = mu[jbeg], mui0 = mu[i0];
+    double mr[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    for (int k0 = 0; k0 < m; k0 += Q) {
-        double z[2 * Q - 1];
-#pragma unroll
-        for (int e = 0; e < 2 * Q - 1; ++e) z[e] = T[rbase + k0 + e];
-#pragma unroll
-        for (int kk = 0; kk < Q; ++kk) {
-            const double yk = ys[k0 + kk];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) acc[q] = fma(z[q + kk], yk, acc[q]);
-        }
+    for (int q = 0; q < Q; ++q) mr[q] = mu[i0 + Q * lane + q];
+    __syncthreads();
+    double sy = 0.0;
+    for (int k = lane; k < m + 64; k += 64) {
+        const double v = k < m ? win[k] - muj : 0.0;
+        win[k] = v;
+        sy += v;
     }
+    Sy = wave_sum(sy);
+    __syncthreads();
+    double st[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] -= mu[rbase + q] * Sy;
+    for (int q = 0; q < Q; ++q) st[q] = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double y = win[k];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) st[q] = fma(area[lane + 64 * q + k], y, st[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) win[lane + 64 * q] = st[q];
+    double sx = 0.0;
+    for (int k = lane; k < m + 64; k += 64) {
+        const double v = k < m ? area[k] - mui0 : 0.0;
+        area[k] = v;
+        sx += v;
+    }
+    Sx = wave_sum(sx);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = win[Q * lane + q] - mr[q] * Sy;
+    __syncthreads();
 }
 
 // Column helpers of one step, staged in LDS per block of 64 columns.
@@ -441,14 +467,21 @@ struct alignas(4 * sizeof(F)) H4 {
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item, in doubles: xs[m+64] | win[max(m+128, 64*PF_T)] | hs[256].
-// win holds the first column's centred window while the initial column is
-// computed, then the T segment of the current block.
+// LDS of a sweep work item, in doubles: area[R_MAX + m] | win[max(m + 128,
+// 64 PF_T, R_MAX)] | hs[256].  area holds the tile's row windows while the
+// first column is computed, then xs (the top row's centred window); win holds
+// the first column's centred window and the transposed first column, then the
+// T segment of the current block.
+__host__ __device__ constexpr int sweep_area_doubles(int m) { return R_MAX + m; }
 __host__ __device__ constexpr int sweep_win_doubles(int m)
 {
-    return (m + 128 > 64 * PF_T) ? m + 128 : 64 * PF_T;
+    return (m + 128 > 64 * PF_T) ? (m + 128 > R_MAX ? m + 128 : R_MAX)
+                                 : (64 * PF_T > R_MAX ? 64 * PF_T : R_MAX);
 }
-__host__ __device__ constexpr int sweep_hs_offset(int m) { return (m + 64 + sweep_win_doubles(m) + 3) & ~3; }
+__host__ __device__ constexpr int sweep_hs_offset(int m)
+{
+    return (sweep_area_doubles(m) + sweep_win_doubles(m) + 3) & ~3;
+}
 __host__ __device__ constexpr size_t sweep_lds_doubles(int m) { return (size_t)(sweep_hs_offset(m) + 256); }
 
 // Staging of one block of 64 columns, software-pipelined: prefetch() issues
@@ -489,21 +522,27 @@ __device__ __forceinline__ void commit(const Prefetch<F>& p, const double* __res
     __syncthreads();  // the previous block is done with win and hs
 #pragma unroll
     for (int q = 0; q < PF_T; ++q) win[lane + 64 * q] = p.tw[q];
-    for (int t = lane + 64 * PF_T; t < m + 68; t += 64) win[t] = T[j0 + t];
+    for (int t = lane + 64 * PF_T; t < m + 72; t += 64) win[t] = T[j0 + t];
     __syncthreads();
+    // B: four independent partial sums, each group of eight LDS reads issued
+    // before its FMAs (xs is zero beyond m, win holds m + 72 values)
     const double* tw = win + lane;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < m; k += 4) {
-        a0 = fma(xs[k], tw[k], a0);
-        a1 = fma(xs[k + 1], tw[k + 1], a1);
-        a2 = fma(xs[k + 2], tw[k + 2], a2);
-        a3 = fma(xs[k + 3], tw[k + 3], a3);
+        double xv[4], tv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xv[u] = xs[k + u];
+            tv[u] = tw[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(xv[u], tv[u], acc[u]);
     }
     H4<F> h;
     h.df = p.df;
     h.dg = p.dg;
     h.inv = p.inv;
-    h.B = (F)((a0 + a1) + (a2 + a3) - p.muj * Sx);
+    h.B = (F)(((acc[0] + acc[1]) + (acc[2] + acc[3])) - p.muj * Sx);
     hs[lane] = h;
     __syncthreads();
 }
@@ -665,6 +704,59 @@ __device__ __forceinline__ void sel_block(const SweepArgs<F>& A, int64_t j0, int
     }
 }
 
+// Margins of every slot after one step of a full block (no masks); returns
+// the lane's largest margin (the column test).
+template <typename F, int Q, int U>
+__device__ __forceinline__ F sel_margins(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
+                                         const F (&nth)[Q], const H4<F>& h, F (&mg)[Q])
+{
+    advance<F, Q, U>(C, a, b, h.df, h.dg, h.B);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) mg[q] = f_fma(C[slot_reg<Q, U>(q)], h.inv, nth[q]);
+    F cm = mg[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) cm = fmax(cm, mg[q]);
+    return cm;
+}
+
+// A full block of 64 steps with every pair a non-self match, in groups of Q
+// steps without per-step tests: row maxima fold two steps per max, column
+// tests are kept as ballots and folded into colbits once per group.
+template <typename F, int Q>
+__device__ __forceinline__ void sel_block_full(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
+                                               const F (&nth)[Q], F (&rm)[Q], const H4<F>* hs,
+                                               unsigned long long& colbits)
+{
+    for (int s0 = 0; s0 < 64; s0 += Q) {
+        H4<F> hv[Q];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
+        unsigned long long bal[Q];
+#define SEL_PAIR(U)                                                                    \
+    {                                                                                  \
+        F m0[Q], m1[Q];                                                                \
+        const F c0 = sel_margins<F, Q, (U)>(C, a, b, nth, hv[(U)], m0);                \
+        bal[(U)] = __ballot(c0 > F(0));                                                \
+        const F c1 = sel_margins<F, Q, (U) + 1>(C, a, b, nth, hv[(U) + 1], m1);        \
+        bal[(U) + 1] = __ballot(c1 > F(0));                                            \
+        _Pragma("unroll") for (int q = 0; q < Q; ++q) rm[q] = fmax(rm[q], fmax(m0[q], m1[q])); \
+    }
+        static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
+        SEL_PAIR(0)
+        if (Q > 2) SEL_PAIR((Q > 2 ? 2 : 0))
+        if (Q > 4) {
+            SEL_PAIR((Q > 4 ? 4 : 0))
+            SEL_PAIR((Q > 4 ? 6 : 0))
+        }
+#undef SEL_PAIR
+        unsigned long long g = 0ull;
+#pragma unroll
+        for (int u = 0; u < Q; ++u)
+            if (bal[u] != 0ull) g |= 1ull << u;
+        colbits |= g << s0;
+    }
+}
+
 template <typename F, int Q>
 __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_t jend, F thr,
                          double* lds, unsigned long long& evals)
@@ -687,14 +779,13 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + (m + 64);
+    double* ys = lds + sweep_area_doubles(m);
     H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m));
     double Sx, Sy;
-    stage_windows(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy);
     F C[Q];
     {
         double acc[Q];
-        initial_column<Q>(A.T, A.mu, m, rbase, ys, Sy, acc);
+        item_start<Q>(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy, acc);
 #pragma unroll
         for (int q = 0; q < Q; ++q) C[q] = (F)acc[q];
     }
@@ -741,7 +832,9 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         const unsigned long long word = load_word(&A.alive[rbase >> 6]);
         unsigned long long colbits = 0ull;
         const bool full = (j - (i0 + R - 1)) >= m;
-        if (full)
+        if (Q <= 4 && full && nst == 64)  // taller tiles: the general path keeps fewer registers
+            sel_block_full<F, Q>(C, a, b, nth, rm, hs, colbits);
+        else if (full)
             sel_block<F, Q, false>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
         else
             sel_block<F, Q, true>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
@@ -850,6 +943,39 @@ __device__ __forceinline__ void ref_block(const SweepArgs<double>& A, int64_t j0
     }
 }
 
+// A full refinement block of 64 steps (every pair valid) in groups of Q
+// steps without per-step tests; row maxima fold two steps per max.
+template <int Q>
+__device__ __forceinline__ void ref_block_full(double (&C)[Q], const double (&a)[Q],
+                                               const double (&b)[Q], double (&mx)[Q],
+                                               const H4<double>* hs)
+{
+    for (int s0 = 0; s0 < 64; s0 += Q) {
+        H4<double> hv[Q];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
+#define REF_PAIR(U)                                                                        \
+    {                                                                                      \
+        double v0[Q], v1[Q];                                                               \
+        advance<double, Q, (U)>(C, a, b, hv[(U)].df, hv[(U)].dg, hv[(U)].B);               \
+        _Pragma("unroll") for (int q = 0; q < Q; ++q) v0[q] =                              \
+            C[slot_reg<Q, (U)>(q)] * hv[(U)].inv;                                          \
+        advance<double, Q, (U) + 1>(C, a, b, hv[(U) + 1].df, hv[(U) + 1].dg, hv[(U) + 1].B); \
+        _Pragma("unroll") for (int q = 0; q < Q; ++q) v1[q] =                              \
+            C[slot_reg<Q, (U) + 1>(q)] * hv[(U) + 1].inv;                                  \
+        _Pragma("unroll") for (int q = 0; q < Q; ++q) mx[q] = fmax(mx[q], fmax(v0[q], v1[q])); \
+    }
+        static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
+        REF_PAIR(0)
+        if (Q > 2) REF_PAIR((Q > 2 ? 2 : 0))
+        if (Q > 4) {
+            REF_PAIR((Q > 4 ? 4 : 0))
+            REF_PAIR((Q > 4 ? 6 : 0))
+        }
+#undef REF_PAIR
+    }
+}
+
 template <int Q>
 __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, int64_t jend,
                          bool left, double thr, int prune, double* lds, unsigned long long& evals)
@@ -873,12 +999,11 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + (m + 64);
+    double* ys = lds + sweep_area_doubles(m);
     H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m));
     double Sx, Sy;
-    stage_windows(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy);
     double C[Q];
-    initial_column<Q>(A.T, A.mu, m, rbase, ys, Sy, C);
+    item_start<Q>(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy, C);
     double a[Q], b[Q], invi[Q], mx[Q];
     int32_t ri[Q];
 #pragma unroll
@@ -913,7 +1038,8 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         bool full;
         if (left) full = (i0 - (j + nst - 1)) >= m;
         else full = (j - (i0 + R - 1)) >= m;
-        if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, hs);
+        if (full && nst == 64) ref_block_full<Q>(C, a, b, mx, hs);
+        else if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, hs);
         else if (left) ref_block<Q, 2>(A, j, nst, C, a, b, mx, ri, hs);
         else ref_block<Q, 1>(A, j, nst, C, a, b, mx, ri, hs);
         ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, left);
@@ -987,7 +1113,8 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
 // Remaining selection work: items (live tile, chunk) drawn nearest-first
 // from each series' counter; a workgroup drains the series in rotated order.
 template <typename F, int Q>
-__global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B, int near_cols, int chunk)
+__global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
+                                                                        int near_cols, int chunk)
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
@@ -1070,7 +1197,8 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
 // Refinement: exact FP64 row maximum of rho over both sides for every tile
 // holding survivors; items drawn nearest-first, alternating right and left.
 template <int Q>
-__global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B, int chunk)
+__global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B,
+                                                                         int chunk)
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
@@ -1326,7 +1454,7 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
     const int64_t j0 = blk * POLISH_COLS;
     double* xg = lds;                          // [POLISH_G][POLISH_KC] candidate chunk
     double* ts = lds + POLISH_G * POLISH_KC;   // T[j0 .. j0 + POLISH_COLS + m)
-    for (int t = tid; t < POLISH_COLS + m; t += POLISH_BLOCK) ts[t] = T[j0 + t];
+    lds_fill(ts, T + j0, POLISH_COLS + m);
     const double feps = c->flat_eps;
     int64_t jc[POLISH_CPT];
     bool colok[POLISH_CPT], flat_j[POLISH_CPT];
@@ -1356,9 +1484,17 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
         for (int kb = 0; kb < m; kb += POLISH_KC) {
             const int kn = min(POLISH_KC, m - kb);
             __syncthreads();  // the previous chunk (and ts) complete / consumed
-            for (int e = tid; e < POLISH_G * POLISH_KC; e += POLISH_BLOCK) {
-                const int g = e / POLISH_KC, k = e - g * POLISH_KC;
-                xg[e] = k < kn ? xc[cidx[g] * stride + kb + k] : 0.0;
+            {
+                constexpr int PER = POLISH_G * POLISH_KC / POLISH_BLOCK;
+                double v[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = tid + POLISH_BLOCK * u;
+                    const int g = e / POLISH_KC, k = e - g * POLISH_KC;
+                    v[u] = k < kn ? xc[cidx[g] * stride + kb + k] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) xg[tid + POLISH_BLOCK * u] = v[u];
             }
             __syncthreads();
             const double* tb = ts + tid + kb;
@@ -1436,7 +1572,8 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
 // partials to each candidate's exact (rho, j), rank the candidates, write the
 // length's top-k rows when the round found at least k range discords, and
 // lower MERLIN's r otherwise; count the series with work left in rem[0].
-__global__ __launch_bounds__(256) void k_round_end(SeriesDev* S, int32_t* rem)
+constexpr int END_BLOCK = 1024;
+__global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* rem)
 {
     __shared__ double nn_s[KP_MAX];
     __shared__ long long id_s[KP_MAX];
@@ -1455,7 +1592,7 @@ __global__ __launch_bounds__(256) void k_round_end(SeriesDev* S, int32_t* rem)
     if (kp >= k) {
         const int64_t npart = s.npart;
         const int64_t nblk = (s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS;
-        for (int cid = w; cid < kp; cid += 4) {
+        for (int cid = w; cid < kp; cid += END_BLOCK / 64) {
             double best = -f_inf<double>(), bj = 1e300;
             for (int64_t p = lane; p < nblk; p += 64) {
                 const double v = s.part[((int64_t)cid * npart + p) * 2];
@@ -1618,7 +1755,7 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
                        dim3((unsigned int)total[PFX_POLISH], (KP_MAX + POLISH_G - 1) / POLISH_G),
                        dim3(POLISH_BLOCK), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
     cfg.timer->end(3, st);
-    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(256), 0, st, bt.s, bt.remaining);
+    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining);
     return hipGetLastError();
 }
 
