@@ -868,7 +868,7 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
     static const int rows_v[] = {128, 256, 512};
     static const int chunk_v[] = {256, 512, 1024, 2048};
     static const int near_v[] = {2048, 8192, 32768, 1 << 30};
-    static const int grid_v[] = {1024, 2048, 3072, 4096, 8192};
+    static const int grid_v[] = {2048, 3072, 4096, 6144, 8192};
     struct Axis {
         int* field;
         const int* vals;

@@ -467,22 +467,26 @@ struct alignas(4 * sizeof(F)) H4 {
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item, in doubles: area[R_MAX + m] | win[max(m + 128,
-// 64 PF_T, R_MAX)] | hs[256].  area holds the tile's row windows while the
-// first column is computed, then xs (the top row's centred window); win holds
-// the first column's centred window and the transposed first column, then the
-// T segment of the current block.
-__host__ __device__ constexpr int sweep_area_doubles(int m) { return R_MAX + m; }
-__host__ __device__ constexpr int sweep_win_doubles(int m)
+// LDS of a sweep work item with R-row tiles, in doubles: area[R + m] |
+// win[max(m + 128, 64 PF_T, R)] | hs[256] | rowv[R] (refinement only: per-row
+// constants read once per block, kept out of registers).  area holds the
+// tile's row windows while the first column is computed, then xs (the top
+// row's centred window); win holds the first column's centred window and the
+// transposed first column, then the T segment of the current block.
+__host__ __device__ constexpr int sweep_area_doubles(int m, int R) { return R + m; }
+__host__ __device__ constexpr int sweep_win_doubles(int m, int R)
 {
-    return (m + 128 > 64 * PF_T) ? (m + 128 > R_MAX ? m + 128 : R_MAX)
-                                 : (64 * PF_T > R_MAX ? 64 * PF_T : R_MAX);
+    return (m + 128 > 64 * PF_T) ? (m + 128 > R ? m + 128 : R) : (64 * PF_T > R ? 64 * PF_T : R);
 }
-__host__ __device__ constexpr int sweep_hs_offset(int m)
+__host__ __device__ constexpr int sweep_hs_offset(int m, int R)
 {
-    return (sweep_area_doubles(m) + sweep_win_doubles(m) + 3) & ~3;
+    return (sweep_area_doubles(m, R) + sweep_win_doubles(m, R) + 3) & ~3;
 }
-__host__ __device__ constexpr size_t sweep_lds_doubles(int m) { return (size_t)(sweep_hs_offset(m) + 256); }
+__host__ __device__ constexpr int sweep_rowv_offset(int m, int R) { return sweep_hs_offset(m, R) + 256; }
+__host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, bool rowv)
+{
+    return (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0));
+}
 
 // Staging of one block of 64 columns, software-pipelined: prefetch() issues
 // the global loads of a block into registers (the T segment up to
@@ -779,8 +783,8 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + sweep_area_doubles(m);
-    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m));
+    double* ys = lds + sweep_area_doubles(m, R);
+    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     F C[Q];
     {
@@ -999,13 +1003,14 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + sweep_area_doubles(m);
-    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m));
+    double* ys = lds + sweep_area_doubles(m, R);
+    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     double C[Q];
     item_start<Q>(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy, C);
-    double a[Q], b[Q], invi[Q], mx[Q];
+    double a[Q], b[Q], mx[Q];
     int32_t ri[Q];
+    double* rowinv = lds + sweep_rowv_offset(m, R);  // 1/(sqrt(m) sigma_i) of the lane's rows
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int64_t i = rbase + q;
@@ -1013,7 +1018,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         const int64_t ip = top ? i : i - 1;
         a[q] = top ? 0.0 : A.df[ip];
         b[q] = top ? 0.0 : A.dg[ip];
-        invi[q] = A.inv[i];
+        rowinv[Q * lane + q] = A.inv[i];
         mx[q] = -f_inf<double>();
         ri[q] = (int32_t)i;
     }
@@ -1046,10 +1051,16 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         j += nst;
         if (prune) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(invi[q] > 0.0 && mx[q] * invi[q] > thr));
+            for (int q = 0; q < Q; ++q) {
+                const double iv = rowinv[Q * lane + q];
+                dm[q] |= uniform64(__ballot(iv > 0.0 && mx[q] * iv > thr));
+            }
         }
         go = sync_rows_with<Q>(A.alive, rbase, word, dm);
     }
+    double invi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) invi[q] = rowinv[Q * lane + q];
     // flat rows: correlation 1 with another flat window, 0 with any other
     const int64_t flo = c->flat_min, fhi = c->flat_max;
     bool flat[Q];
@@ -1197,7 +1208,7 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
 // Refinement: exact FP64 row maximum of rho over both sides for every tile
 // holding survivors; items drawn nearest-first, alternating right and left.
 template <int Q>
-__global__ __launch_bounds__(64) void k_refine(SeriesDev* S, int B,
+__global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_refine(SeriesDev* S, int B,
                                                                          int chunk)
 {
     extern __shared__ double lds[];
@@ -1679,7 +1690,7 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
 template <typename F, int Q>
 static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, false);
     if (total[PFX_NEAR] == 0) return;
     cfg.timer->begin(0, st);
     hipLaunchKernelGGL((k_select_near<F, Q>), dim3((unsigned int)total[PFX_NEAR]), dim3(64), lds,
@@ -1690,7 +1701,7 @@ static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
 template <typename F, int Q>
 static void launch_far(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, false);
     hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TSEL]), dim3(256), 0, st, bt.s, bt.B,
                        bt.pfx[PFX_TSEL], 64 * Q, 0, cfg.near_cols, cfg.chunk_cols);
     cfg.timer->begin(1, st);
@@ -1704,7 +1715,7 @@ static void launch_refine(const Batch& bt, const SweepCfg& cfg, const int64_t* t
 {
     hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TREF]), dim3(256), 0, st, bt.s, bt.B,
                        bt.pfx[PFX_TREF], 64 * Q, 1, 0, cfg.chunk_cols);
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, true);
     cfg.timer->begin(2, st);
     hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
                        cfg.chunk_cols);

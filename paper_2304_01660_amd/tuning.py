@@ -20,7 +20,7 @@ import sys
 TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
 
 # workload name -> (probe lengths, timed runs per configuration)
-PROBES = {"single": (8, 2), "batch": (6, 1)}
+PROBES = {"single": (8, 2), "batch": (12, 1)}
 
 
 def options(name: str) -> dict:
