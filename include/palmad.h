@@ -24,8 +24,8 @@
  *     device; the library never frees or retains them.  A call runs on the
  *     context's own stream, after the work already queued on the HIP stream
  *     given to the call and before any work queued there later; it returns
- *     once the result is complete (the adaptive r loop reads one counter per
- *     round of range searches).
+ *     once the result is complete (the adaptive r loop reads one counter
+ *     every few rounds of range searches).
  *   - Every function returns a palmad_status.  Arguments are validated on
  *     the host before any device work; on error nothing is written to the
  *     outputs and palmad_last_error() describes the problem.  No C++

@@ -5,8 +5,8 @@
 // series (one series for the plain entry points): per round, every series
 // with work left performs one range search (one DRAG call of Alg. 2,
 // parallelised as in Sec. 3.2-3.3) at its own length.  The driver replays
-// the round as a hipGraph on the context's stream and reads one counter per
-// round to learn whether any series still has work.
+// a few rounds at a time as a hipGraph on the context's stream and then
+// reads one counter to learn whether any series still has work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -342,19 +342,30 @@ void drop_graph(palmad_ctx* ctx)
     ctx->graph_key.clear();
 }
 
-// One round: replayed from the context's cached graph (captured on first use
-// for this workspace and configuration), or launched directly.
-int run_round(palmad_ctx* ctx, const Batch& bt, const SweepCfg& cfg, const Plan& p, bool graphs)
+// Rounds replayed per host check: a finished series makes every kernel of
+// a round return at once, so a few rounds past the end cost little, while
+// each check is a device-to-host copy and a stream synchronisation.
+constexpr int ROUNDS_PER_CHECK = 4;
+
+// ROUNDS_PER_CHECK rounds replayed from the context's cached graph (captured
+// on first use for this workspace and configuration), or one round launched
+// directly.  Returns the number of rounds issued in *issued.
+int run_rounds(palmad_ctx* ctx, const Batch& bt, const SweepCfg& cfg, const Plan& p, bool graphs,
+               int* issued)
 {
     if (!graphs) {
         HIP_TRY(launch_round(bt, cfg, p.totals, ctx->work));
+        *issued = 1;
         return PALMAD_OK;
     }
+    *issued = ROUNDS_PER_CHECK;
     const std::string key = graph_key(bt, cfg, p);
     if (ctx->graph_exec == nullptr || ctx->graph_key != key) {
         drop_graph(ctx);
         HIP_TRY(hipStreamBeginCapture(ctx->work, hipStreamCaptureModeThreadLocal));
-        const hipError_t e = launch_round(bt, cfg, p.totals, ctx->work);
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < ROUNDS_PER_CHECK && e == hipSuccess; ++r)
+            e = launch_round(bt, cfg, p.totals, ctx->work);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(ctx->work, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -423,10 +434,12 @@ int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double
     int64_t max_rounds = 0;
     for (int b = 0; b < p.B; ++b) max_rounds = std::max<int64_t>(max_rounds, p.lay[b].L);
     max_rounds = max_rounds * MAX_ATTEMPTS + 2;
-    for (int64_t round = 0;; ++round) {
+    for (int64_t round = 0;;) {
         if (round > max_rounds) return fail(ctx, PALMAD_EDEVICE, "search did not terminate");
-        rc = run_round(ctx, bt, cfg, p, graphs);
+        int issued = 0;
+        rc = run_rounds(ctx, bt, cfg, p, graphs, &issued);
         if (rc) return rc;
+        round += issued;
         HIP_TRY(hipMemcpyAsync(ctx->pinned, bt.remaining, 2 * sizeof(int32_t),
                                hipMemcpyDeviceToHost, ctx->work));
         HIP_TRY(hipStreamSynchronize(ctx->work));

@@ -165,7 +165,7 @@ __device__ __forceinline__ unsigned long long pair_count(long long ilo, long lon
 // searched again with the r that k_round_end lowered.  Then set the range of
 // this round, its pruning threshold and reset the round's work counters.
 // rem[0] (series with work left after the round, counted by k_round_end) and
-// rem[1] (series that gave up) start at zero here.
+// rem[1] (series that gave up, now or in an earlier round) start at zero here.
 __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
 {
     const int li = c->li;
@@ -221,6 +221,7 @@ __global__ void k_round_prep(SeriesDev* S, int B, float guard, int32_t* rem)
         Ctrl* c = s.ctrl;
         if (c->finished) {
             c->active = 0;
+            if (c->error) atomicAdd(&rem[1], 1);  // stays visible in later rounds
             continue;
         }
         if (!c->started) {
@@ -1465,7 +1466,6 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
     const int64_t j0 = blk * POLISH_COLS;
     double* xg = lds;                          // [POLISH_G][POLISH_KC] candidate chunk
     double* ts = lds + POLISH_G * POLISH_KC;   // T[j0 .. j0 + POLISH_COLS + m)
-    lds_fill(ts, T + j0, POLISH_COLS + m);
     const double feps = c->flat_eps;
     int64_t jc[POLISH_CPT];
     bool colok[POLISH_CPT], flat_j[POLISH_CPT];
@@ -1504,6 +1504,8 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
                     const int g = e / POLISH_KC, k = e - g * POLISH_KC;
                     v[u] = k < kn ? xc[cidx[g] * stride + kb + k] : 0.0;
                 }
+                // the columns' values travel together with the first chunk
+                if (kb == 0) lds_fill(ts, T + j0, POLISH_COLS + m);
 #pragma unroll
                 for (int u = 0; u < PER; ++u) xg[tid + POLISH_BLOCK * u] = v[u];
             }
