@@ -31,10 +31,18 @@ constexpr int MAX_ATTEMPTS = 5000;
 // the refinement sweep: the exact pass evaluates all of them directly.
 constexpr int DIRECT_MAX = KP_MAX;
 
+// Pair-evaluation counters: EV_SLOTS slots per class, so that the many
+// work items of a launch add to different addresses.
+constexpr int EV_CLASSES = 4;  // first selection pass, split pass, refinement, exact pass
+constexpr int EV_SLOTS = 64;
+enum { EV_NEAR = 0, EV_FAR = 1, EV_REF = 2, EV_POL = 3 };
+
 // Device-resident control block of one series (the MERLIN state of Alg. 1
-// plus the work counters of the current round).
+// plus the work counters of the current round).  Fields that work items
+// update with atomics sit on cache lines of their own, away from the fields
+// every item reads.
 struct Ctrl {
-    // controller
+    // controller (read by every work item)
     double r;          // current range (ED units)
     double step;       // decrement of the later-length rule
     double thr64;      // pruning threshold on the correlation: 1 - r^2/(2m); >= 1 disables
@@ -54,17 +62,18 @@ struct Ctrl {
     int32_t nonfinite; // set when the series holds NaN/Inf
     double flat_eps;   // sigma threshold of a flat window
     double sigmaT;     // population sigma of the whole series
-    // work lists of the current round
-    uint32_t nlive_sel, maxc_sel;  // live selection tiles, most chunks of one tile
+    int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
+    // work lists of the current round (built by k_tiles, read by the queued passes)
+    alignas(128) uint32_t nlive_sel, maxc_sel;  // live selection tiles, most chunks of one tile
     uint32_t nlive_ref, maxc_ref;
-    unsigned long long ctr_sel, ctr_ref;  // work-queue heads (items: chunk-major)
+    uint32_t live_ref;     // live subsequences entering refinement this round
     uint32_t nsurv;
     uint32_t ncand;
-    uint32_t live_ref;     // live subsequences entering refinement this round
-    int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
+    // work-queue heads (items: chunk-major)
+    alignas(128) unsigned long long ctr_sel;
+    alignas(128) unsigned long long ctr_ref;
     // counters accumulated over the call
-    unsigned long long evals_sel, evals_ref, evals_pol, rounds, survivors;
-    unsigned long long evals_near, evals_far;
+    alignas(128) unsigned long long rounds, survivors;
     unsigned long long rows_near, rows_far;  // live rows entering the split / refinement passes
 };
 
@@ -94,6 +103,7 @@ struct SeriesDev {
     double* part;        // polish partials [KP_MAX * npart * 2 + tail]
     double* xc;          // centred candidate windows [KP_MAX][maxL + 8], then their sums
     double* hist;        // nnDist history per length [L]
+    unsigned long long* evc;  // pair evaluations [EV_CLASSES][EV_SLOTS]
     double* red;         // reduction scratch [2 * RED_BLOCKS]
     Ctrl* ctrl;
     // outputs (rows of this series; NULL for a bare range search)
@@ -109,7 +119,7 @@ struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
     size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho,
-        off_tsel, off_tref, off_cand, off_part, off_xc, off_hist, off_ctrl, off_red, total;
+        off_tsel, off_tref, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
 SeriesDev carve(void* base, const Layout& lay);

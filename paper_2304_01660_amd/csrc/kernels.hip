@@ -1117,8 +1117,7 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
     unsigned long long ev = 0;
     sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
     if (threadIdx.x == 0 && ev) {
-        atomicAdd(&c->evals_sel, ev);
-        atomicAdd(&c->evals_near, ev);
+        atomicAdd(&s.evc[EV_NEAR * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
     }
 }
 
@@ -1156,8 +1155,7 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
             sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
         }
         if (threadIdx.x == 0 && ev) {
-            atomicAdd(&c->evals_sel, ev);
-            atomicAdd(&c->evals_far, ev);
+            atomicAdd(&s.evc[EV_FAR * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
         }
     }
 }
@@ -1261,7 +1259,8 @@ __global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_refine(SeriesDev* S, i
             if (jbeg >= jend) continue;
             ref_item<Q>(A, i0, jbeg, jend, left, thr, prune, lds, ev);
         }
-        if (threadIdx.x == 0 && ev) atomicAdd(&c->evals_ref, ev);
+        if (threadIdx.x == 0 && ev)
+            atomicAdd(&s.evc[EV_REF * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
     }
 }
 
@@ -1578,7 +1577,9 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
         }
     }
     ev = (unsigned long long)wave_sum((double)ev);
-    if ((tid & 63) == 0 && ev) atomicAdd(&c->evals_pol, ev);
+    if ((tid & 63) == 0 && ev)
+        atomicAdd(&s.evc[EV_POL * EV_SLOTS + ((blockIdx.x + blockIdx.y + (tid >> 6)) & (EV_SLOTS - 1))],
+                  ev);
 }
 
 // Close the round of every series (one block each): reduce the polish
@@ -1825,19 +1826,25 @@ __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
     __shared__ unsigned long long acc[9];
     if (threadIdx.x < 9) acc[threadIdx.x] = 0ull;
     __syncthreads();
-    for (int b = threadIdx.x; b < B; b += blockDim.x) {
-        const Ctrl* c = S[b].ctrl;
-        atomicAdd(&acc[0], c->evals_sel);
-        atomicAdd(&acc[1], c->evals_ref);
-        atomicAdd(&acc[2], c->evals_pol);
-        atomicAdd(&acc[3], c->rounds);
-        atomicAdd(&acc[4], c->survivors);
-        atomicAdd(&acc[5], c->evals_near);
-        atomicAdd(&acc[6], c->evals_far);
-        atomicAdd(&acc[7], c->rows_near);
-        atomicAdd(&acc[8], c->rows_far);
+    for (int b = 0; b < B; ++b) {
+        const SeriesDev& s = S[b];
+        for (int e = threadIdx.x; e < EV_CLASSES * EV_SLOTS; e += blockDim.x) {
+            const unsigned long long v = s.evc[e];
+            const int cls = e / EV_SLOTS;
+            if (v) {
+                if (cls == EV_NEAR || cls == EV_FAR) atomicAdd(&acc[0], v);
+                atomicAdd(&acc[cls == EV_NEAR ? 5 : cls == EV_FAR ? 6 : cls == EV_REF ? 1 : 2], v);
+            }
+        }
+        if (threadIdx.x == 0) {
+            const Ctrl* c = s.ctrl;
+            acc[3] += c->rounds;
+            acc[4] += c->survivors;
+            acc[7] += c->rows_near;
+            acc[8] += c->rows_far;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x < 9) out[threadIdx.x] = acc[threadIdx.x];
 }
 
@@ -1923,6 +1930,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_part = o;  o = al256(o + sizeof(double) * (size_t)(2 * KP_MAX * (l.npart + 1)));
     l.off_xc = o;    o = al256(o + sizeof(double) * (size_t)KP_MAX * (size_t)(maxL + 9));
     l.off_hist = o;  o = al256(o + sizeof(double) * (size_t)(l.L > 0 ? l.L : 1));
+    l.off_evc = o;   o = al256(o + sizeof(unsigned long long) * EV_CLASSES * EV_SLOTS);
     l.off_ctrl = o;  o = al256(o + sizeof(Ctrl));
     l.off_red = o;   o = al256(o + sizeof(double) * 2 * RED_BLOCKS);
     l.total = o;
@@ -1965,6 +1973,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.part = (double*)(p + l.off_part);
     s.xc = (double*)(p + l.off_xc);
     s.hist = (double*)(p + l.off_hist);
+    s.evc = (unsigned long long*)(p + l.off_evc);
     s.ctrl = (Ctrl*)(p + l.off_ctrl);
     s.red = (double*)(p + l.off_red);
     return s;
