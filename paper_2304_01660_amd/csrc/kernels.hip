@@ -422,12 +422,27 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
 {
     constexpr int R = 64 * Q;
     const int lane = threadIdx.x;
-    lds_fill(area, T + i0, R + m);
-    lds_fill(win, T + jbeg, m);
     const double muj = mu[jbeg], mui0 = mu[i0];
     double mr[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) mr[q] = mu[i0 + Q * lane + q];
+    // one burst of loads: the column window first (it is needed first), then
+    // the rows' windows
+    {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = lane + 64 * u;
+            v[u] = t < m ? T[jbeg + t] : 0.0;
+        }
+        lds_fill(area, T + i0, R + m + 4);
+        for (int t = lane + 256; t < m; t += 64) win[t] = T[jbeg + t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = lane + 64 * u;
+            if (t < m) win[t] = v[u];
+        }
+    }
     __syncthreads();
     double sy = 0.0;
     for (int k = lane; k < m + 64; k += 64) {
@@ -440,10 +455,20 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
     double st[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) st[q] = 0.0;
-    for (int k = 0; k < m; ++k) {
-        const double y = win[k];
+    // strided rows: lane l holds rows l + 64 q; four offsets per pass with
+    // their LDS reads issued together (win is zero from m to m + 64)
+    for (int k = 0; k < m; k += 4) {
+        double y[4], t[4][Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) st[q] = fma(area[lane + 64 * q + k], y, st[q]);
+        for (int u = 0; u < 4; ++u) {
+            y[u] = win[k + u];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) t[u][q] = area[lane + 64 * q + k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) st[q] = fma(t[u][q], y[u], st[q]);
     }
     __syncthreads();
 #pragma unroll
@@ -468,13 +493,13 @@ struct alignas(4 * sizeof(F)) H4 {
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item with R-row tiles, in doubles: area[R + m] |
+// LDS of a sweep work item with R-row tiles, in doubles: area[R + m + 4] |
 // win[max(m + 128, 64 PF_T, R)] | hs[256] | rowv[R] (refinement only: per-row
 // constants read once per block, kept out of registers).  area holds the
 // tile's row windows while the first column is computed, then xs (the top
 // row's centred window); win holds the first column's centred window and the
 // transposed first column, then the T segment of the current block.
-__host__ __device__ constexpr int sweep_area_doubles(int m, int R) { return R + m; }
+__host__ __device__ constexpr int sweep_area_doubles(int m, int R) { return R + m + 4; }
 __host__ __device__ constexpr int sweep_win_doubles(int m, int R)
 {
     return (m + 128 > 64 * PF_T) ? (m + 128 > R ? m + 128 : R) : (64 * PF_T > R ? 64 * PF_T : R);
