@@ -409,7 +409,8 @@ __device__ __forceinline__ void lds_fill(double* dst, const double* __restrict__
 // i0, first column jbeg):
 //  * acc[q] = C(rbase + q, jbeg), rbase = i0 + Q lane: centred dot products
 //    sum_k t_{i+k} y_k - mu_i Sy with y the centred window of column jbeg.
-//    The rows' windows are staged in LDS (area: R + m values) and evaluated
+//    The rows' windows are staged in LDS (area: R + m + 4 values, the tail
+//    read by the last unrolled step of the dot products) and evaluated
 //    with lane l taking rows l, l + 64, ... (conflict-free LDS reads), then
 //    transposed through LDS to the lane's contiguous rows;
 //  * area then holds xs, the centred window of the tile's top row zero padded
