@@ -30,6 +30,9 @@ constexpr int MAX_ATTEMPTS = 5000;
 // A round whose selection leaves at most this many live subsequences skips
 // the refinement sweep: the exact pass evaluates all of them directly.
 constexpr int DIRECT_MAX = KP_MAX;
+// Row tiles that held survivors at the end of a round (at most HOT_MAX of
+// them) lead the next round's first selection pass.
+constexpr int HOT_MAX = 64;
 
 // Pair-evaluation counters: EV_SLOTS slots per class, so that the many
 // work items of a launch add to different addresses.
@@ -63,6 +66,8 @@ struct Ctrl {
     double flat_eps;   // sigma threshold of a flat window
     double sigmaT;     // population sigma of the whole series
     int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
+    uint32_t nhot;     // entries of SeriesDev::hot (set by k_round_end)
+    int32_t hot_r;     // tile height the hot list was built for
     // work lists of the current round (built by k_tiles, read by the queued passes)
     alignas(128) uint32_t nlive_sel, maxc_sel;  // live selection tiles, most chunks of one tile
     uint32_t nlive_ref, maxc_ref;
@@ -99,6 +104,7 @@ struct SeriesDev {
     unsigned long long* rho;     // ordered-bits row max correlation [Npad]
     int32_t* tsel;       // live selection tiles
     int32_t* tref;       // live refinement tiles
+    int32_t* hot;        // tiles holding survivors after the last round, ascending [HOT_MAX]
     int64_t* cand;       // polished candidates [KP_MAX]
     double* part;        // polish partials [KP_MAX * npart * 2 + tail]
     double* xc;          // centred candidate windows [KP_MAX][maxL + 8], then their sums
@@ -119,7 +125,7 @@ struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
     size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho,
-        off_tsel, off_tref, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
+        off_tsel, off_tref, off_hot, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
 SeriesDev carve(void* base, const Layout& lay);

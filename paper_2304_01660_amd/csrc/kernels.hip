@@ -750,19 +750,12 @@ __device__ __forceinline__ F sel_margins(F (&C)[Q], const F (&a)[Q], const F (&b
     return cm;
 }
 
-// A full block of 64 steps with every pair a non-self match, in groups of Q
-// steps without per-step tests: row maxima fold two steps per max, column
-// tests are kept as ballots and folded into colbits once per group.
 template <typename F, int Q>
-__device__ __forceinline__ void sel_block_full(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
-                                               const F (&nth)[Q], F (&rm)[Q], const H4<F>* hs,
-                                               unsigned long long& colbits)
+__device__ __forceinline__ void sel_group(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
+                                          const F (&nth)[Q], F (&rm)[Q], const H4<F> (&hv)[Q],
+                                          unsigned long long& colbits, int s0)
 {
-    for (int s0 = 0; s0 < 64; s0 += Q) {
-        H4<F> hv[Q];
-#pragma unroll
-        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
-        unsigned long long bal[Q];
+    unsigned long long bal[Q];
 #define SEL_PAIR(U)                                                                    \
     {                                                                                  \
         F m0[Q], m1[Q];                                                                \
@@ -772,19 +765,36 @@ __device__ __forceinline__ void sel_block_full(F (&C)[Q], const F (&a)[Q], const
         bal[(U) + 1] = __ballot(c1 > F(0));                                            \
         _Pragma("unroll") for (int q = 0; q < Q; ++q) rm[q] = fmax(rm[q], fmax(m0[q], m1[q])); \
     }
-        static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
-        SEL_PAIR(0)
-        if (Q > 2) SEL_PAIR((Q > 2 ? 2 : 0))
-        if (Q > 4) {
-            SEL_PAIR((Q > 4 ? 4 : 0))
-            SEL_PAIR((Q > 4 ? 6 : 0))
-        }
+    static_assert(Q == 2 || Q == 4 || Q == 8, "Q must be 2, 4 or 8");
+    SEL_PAIR(0)
+    if (Q > 2) SEL_PAIR((Q > 2 ? 2 : 0))
+    if (Q > 4) {
+        SEL_PAIR((Q > 4 ? 4 : 0))
+        SEL_PAIR((Q > 4 ? 6 : 0))
+    }
 #undef SEL_PAIR
-        unsigned long long g = 0ull;
+    unsigned long long g = 0ull;
 #pragma unroll
-        for (int u = 0; u < Q; ++u)
-            if (bal[u] != 0ull) g |= 1ull << u;
-        colbits |= g << s0;
+    for (int u = 0; u < Q; ++u)
+        if (bal[u] != 0ull) g |= 1ull << u;
+    colbits |= g << s0;
+}
+
+// A full block of 64 steps with every pair a non-self match, in groups of Q
+// steps without per-step tests: row maxima fold two steps per max, column
+// tests are kept as ballots and folded into colbits once per group.  (Reading
+// the next group's helpers ahead costs registers, hence occupancy, and
+// measured slower.)
+template <typename F, int Q>
+__device__ __forceinline__ void sel_block_full(F (&C)[Q], const F (&a)[Q], const F (&b)[Q],
+                                               const F (&nth)[Q], F (&rm)[Q], const H4<F>* hs,
+                                               unsigned long long& colbits)
+{
+    for (int s0 = 0; s0 < 64; s0 += Q) {
+        H4<F> hv[Q];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) hv[u] = hs[s0 + u];
+        sel_group<F, Q>(C, a, b, nth, rm, hv, colbits, s0);
     }
 }
 
@@ -1130,13 +1140,41 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
     constexpr int R = 64 * Q;
     const int64_t lb = blockIdx.x - pfx[b];
     const SweepArgs<F> A = args_of<F>(s, c);
-    // chunk-major: every tile's nearest chunk is dispatched first, so later
-    // chunks find the rows their neighbours already pruned
+    // The series' blocks enumerate (tile, chunk) pairs: first every chunk of
+    // the hot tiles (those that held survivors after the last round), then
+    // the other tiles; both parts chunk-major, so that every tile's nearest
+    // chunk is dispatched before its later ones, which then find the rows
+    // their neighbours already pruned.
     const int64_t ntiles = (s.Nmax + R - 1) / R;
-    const int64_t i0 = (lb % ntiles) * R;
+    const int64_t nsub = (pfx[b + 1] - pfx[b]) / ntiles;
+    const unsigned int nhot = c->hot_r == R ? c->nhot : 0u;
+    int64_t tile, cc;
+    if (nhot == 0u) {
+        tile = lb % ntiles;
+        cc = lb / ntiles;
+    } else {
+        const int lane = threadIdx.x;
+        const int hv = lane < (int)nhot ? s.hot[lane] : 0x7fffffff;
+        const int64_t nh = (int64_t)nhot * nsub;
+        if (lb < nh) {
+            // rotated by the chunk so that one tile's chunks do not all fall
+            // on the same XCD when nhot is a multiple of the XCD count
+            cc = lb / nhot;
+            tile = __builtin_amdgcn_readlane(hv, (int)((lb + cc) % nhot));
+        } else {
+            // the r-th tile that is not hot is r + #{i : hot[i] - i <= r}
+            const int64_t x = lb - nh;
+            const int64_t rest = ntiles - nhot;
+            if (rest <= 0) return;
+            const int64_t r = x % rest;
+            cc = x / rest;
+            tile = r + __popcll(__ballot(lane < (int)nhot && (int64_t)(hv - lane) <= r));
+        }
+    }
+    const int64_t i0 = tile * R;
     if (i0 >= A.N) return;
     const int64_t j00 = i0 + A.m;
-    const int64_t jbeg = j00 + (lb / ntiles) * chunk;
+    const int64_t jbeg = j00 + cc * chunk;
     if (jbeg >= A.N || jbeg >= j00 + near_cols) return;
     const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
     const F thr = sel_threshold<F>(c);
@@ -1613,7 +1651,7 @@ __global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
 // length's top-k rows when the round found at least k range discords, and
 // lower MERLIN's r otherwise; count the series with work left in rem[0].
 constexpr int END_BLOCK = 1024;
-__global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* rem)
+__global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* rem, int hot_rows)
 {
     __shared__ double nn_s[KP_MAX];
     __shared__ long long id_s[KP_MAX];
@@ -1711,6 +1749,46 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
         }
         if (!(c->done && c->m >= s.maxL)) atomicAdd(&rem[0], 1);
     }
+    // Tiles of hot_rows rows that still hold survivors, in ascending order
+    // (the first HOT_MAX of them): the next round's first selection pass
+    // dispatches all their chunks before any other tile's, so that the
+    // longest work items of the pass start first.
+    __shared__ unsigned int wcnt_s[END_BLOCK / 64];
+    __shared__ unsigned int base_s;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) base_s = 0;
+    const int64_t ntl = (s.n - m + 1 + hot_rows - 1) / hot_rows;
+    const int wpt = hot_rows / 64;
+    for (int64_t t0 = 0; t0 < ntl; t0 += END_BLOCK) {
+        __syncthreads();
+        const unsigned int base = base_s;
+        const int64_t t = t0 + tid;
+        bool hot = false;
+        if (t < ntl) {
+            unsigned long long any = 0ull;
+            for (int w2 = 0; w2 < wpt; ++w2) any |= load_word(&s.alive[t * wpt + w2]);
+            hot = any != 0ull;
+        }
+        const unsigned long long bal = __ballot(hot);
+        if (lane == 0) wcnt_s[w] = (unsigned int)__popcll(bal);
+        __syncthreads();
+        unsigned int before = 0, total = 0;
+        for (int q = 0; q < END_BLOCK / 64; ++q) {
+            before += (q < w) ? wcnt_s[q] : 0u;
+            total += wcnt_s[q];
+        }
+        const unsigned int pos =
+            base + before + (unsigned int)__popcll(bal & ((1ull << lane) - 1ull));
+        if (hot && pos < (unsigned int)HOT_MAX) s.hot[pos] = (int32_t)t;
+        __syncthreads();
+        if (tid == 0) base_s = base + total;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        c->nhot = base_s < (unsigned int)HOT_MAX ? base_s : (unsigned int)HOT_MAX;
+        c->hot_r = hot_rows;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1795,7 +1873,8 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
                        dim3((unsigned int)total[PFX_POLISH], (KP_MAX + POLISH_G - 1) / POLISH_G),
                        dim3(POLISH_BLOCK), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
     cfg.timer->end(3, st);
-    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining);
+    hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining,
+                       64 * cfg.q_near);
     return hipGetLastError();
 }
 
@@ -1952,6 +2031,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_rho = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
     l.off_tsel = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_tref = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
+    l.off_hot = o;   o = al256(o + sizeof(int32_t) * (size_t)HOT_MAX);
     l.off_cand = o;  o = al256(o + sizeof(int64_t) * (size_t)KP_MAX);
     l.off_part = o;  o = al256(o + sizeof(double) * (size_t)(2 * KP_MAX * (l.npart + 1)));
     l.off_xc = o;    o = al256(o + sizeof(double) * (size_t)KP_MAX * (size_t)(maxL + 9));
@@ -1995,6 +2075,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.rho = (unsigned long long*)(p + l.off_rho);
     s.tsel = (int32_t*)(p + l.off_tsel);
     s.tref = (int32_t*)(p + l.off_tref);
+    s.hot = (int32_t*)(p + l.off_hot);
     s.cand = (int64_t*)(p + l.off_cand);
     s.part = (double*)(p + l.off_part);
     s.xc = (double*)(p + l.off_xc);
