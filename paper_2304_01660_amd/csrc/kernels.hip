@@ -405,30 +405,77 @@ __device__ __forceinline__ void lds_fill(double* dst, const double* __restrict__
     }
 }
 
+// LDS index of value p of the tile's row windows while the first column is
+// computed: one pad value after every Q, so that lanes reading values Q apart
+// (each lane holds Q consecutive rows) hit distinct banks.
+template <int Q>
+__device__ __forceinline__ int skw(int p)
+{
+    return p + p / Q;
+}
+
+// lds_fill into the skewed layout.
+template <int Q>
+__device__ __forceinline__ void lds_fill_skew(double* dst, const double* __restrict__ src, int count)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int base = 0; base < count; base += nt * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = base + tid + nt * u;
+            v[u] = t < count ? src[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = base + tid + nt * u;
+            if (t < count) dst[skw<Q>(t)] = v[u];
+        }
+    }
+}
+
 // Start of a sweep work item (one wavefront, row tile of R = 64 Q rows from
 // i0, first column jbeg):
 //  * acc[q] = C(rbase + q, jbeg), rbase = i0 + Q lane: centred dot products
-//    sum_k t_{i+k} y_k - mu_i Sy with y the centred window of column jbeg.
-//    The rows' windows are staged in LDS (area: R + m + 4 values, the tail
-//    read by the last unrolled step of the dot products) and evaluated
-//    with lane l taking rows l, l + 64, ... (conflict-free LDS reads), then
-//    transposed through LDS to the lane's contiguous rows;
-//  * area then holds xs, the centred window of the tile's top row zero padded
-//    by 64, with sum Sx (zero up to rounding), for the top-boundary values.
-// win must hold max(m + 64, R) values.
+//    sum_k t_{i+k} y_k - mu_i Sy with y the centred window of column jbeg
+//    (staged in xs).  The rows' windows are staged in sk (skewed); each lane
+//    walks its Q consecutive rows along k with a ring of P row values, so
+//    that one LDS read per step serves all Q rows and is issued P - Q + 1
+//    steps before its first use;
+//  * xs then holds the centred window of the tile's top row zero padded by
+//    64, with sum Sx (zero up to rounding), for the top-boundary values, and
+//    sk is free again.
+// xs must hold m + 64 values, sk sweep_skew_doubles(m, R).
+template <int Q>
+__host__ __device__ constexpr int start_ring()
+{
+    return Q <= 4 ? 2 * Q : Q;  // the tallest tiles have no registers to spare
+}
+template <int Q>
+__host__ __device__ constexpr int start_steps(int m)
+{
+    return ((m + start_ring<Q>() - 1) / start_ring<Q>()) * start_ring<Q>();
+}
+template <int Q>
+__host__ __device__ constexpr int start_rows(int m)
+{
+    return 64 * Q + start_steps<Q>(m) + start_ring<Q>();
+}
+
 template <int Q>
 __device__ void item_start(const double* __restrict__ T, const double* __restrict__ mu, int32_t m,
-                           int64_t i0, int64_t jbeg, double* area, double* win, double& Sx,
+                           int64_t i0, int64_t jbeg, double* xs, double* sk, double& Sx,
                            double& Sy, double (&acc)[Q])
 {
-    constexpr int R = 64 * Q;
+    constexpr int P = start_ring<Q>();  // ring of row values
     const int lane = threadIdx.x;
+    const int mp = start_steps<Q>(m);
     const double muj = mu[jbeg], mui0 = mu[i0];
     double mr[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) mr[q] = mu[i0 + Q * lane + q];
-    // one burst of loads: the column window first (it is needed first), then
-    // the rows' windows
+    // one burst of loads: the column window (xs, zero from m on) first, it is
+    // needed first, then the rows' windows
     {
         double v[4];
 #pragma unroll
@@ -436,54 +483,50 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
             const int t = lane + 64 * u;
             v[u] = t < m ? T[jbeg + t] : 0.0;
         }
-        lds_fill(area, T + i0, R + m + 4);
-        for (int t = lane + 256; t < m; t += 64) win[t] = T[jbeg + t];
+        lds_fill_skew<Q>(sk, T + i0, start_rows<Q>(m));
+        for (int t = lane + 256; t < m + 64; t += 64) xs[t] = t < m ? T[jbeg + t] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = lane + 64 * u;
-            if (t < m) win[t] = v[u];
+            if (t < m + 64) xs[t] = v[u];
         }
     }
     __syncthreads();
     double sy = 0.0;
-    for (int k = lane; k < m + 64; k += 64) {
-        const double v = k < m ? win[k] - muj : 0.0;
-        win[k] = v;
+    for (int k = lane; k < m; k += 64) {
+        const double v = xs[k] - muj;
+        xs[k] = v;
         sy += v;
     }
     Sy = wave_sum(sy);
     __syncthreads();
-    double st[Q];
+    // ring slot (k + q) mod P holds row value Q lane + k + q at step k; the
+    // slot row 0 used last is refilled P values ahead
+    const int base = Q * lane;
+    double st[Q], r[P];
 #pragma unroll
     for (int q = 0; q < Q; ++q) st[q] = 0.0;
-    // strided rows: lane l holds rows l + 64 q; four offsets per pass with
-    // their LDS reads issued together (win is zero from m to m + 64)
-    for (int k = 0; k < m; k += 4) {
-        double y[4], t[4][Q];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            y[u] = win[k + u];
+    for (int u = 0; u < P; ++u) r[u] = sk[skw<Q>(base + u)];
+    for (int k0 = 0; k0 < mp; k0 += P) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) t[u][q] = area[lane + 64 * q + k + u];
+        for (int u = 0; u < P; ++u) {
+            const double y = xs[k0 + u];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) st[q] = fma(r[(u + q) % P], y, st[q]);
+            r[u] = sk[skw<Q>(base + k0 + u + P)];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int q = 0; q < Q; ++q) st[q] = fma(t[u][q], y[u], st[q]);
     }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < Q; ++q) win[lane + 64 * q] = st[q];
+    for (int q = 0; q < Q; ++q) acc[q] = st[q] - mr[q] * Sy;
+    __syncthreads();
     double sx = 0.0;
     for (int k = lane; k < m + 64; k += 64) {
-        const double v = k < m ? area[k] - mui0 : 0.0;
-        area[k] = v;
+        const double v = k < m ? sk[skw<Q>(k)] - mui0 : 0.0;
+        xs[k] = v;
         sx += v;
     }
     Sx = wave_sum(sx);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = win[Q * lane + q] - mr[q] * Sy;
     __syncthreads();
 }
 
@@ -494,25 +537,35 @@ struct alignas(4 * sizeof(F)) H4 {
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item with R-row tiles, in doubles: area[R + m + 4] |
-// win[max(m + 128, 64 PF_T, R)] | hs[256] | rowv[R] (refinement only: per-row
-// constants read once per block, kept out of registers).  area holds the
-// tile's row windows while the first column is computed, then xs (the top
-// row's centred window); win holds the first column's centred window and the
-// transposed first column, then the T segment of the current block.
-__host__ __device__ constexpr int sweep_area_doubles(int m, int R) { return R + m + 4; }
+// LDS of a sweep work item with R = 64 Q row tiles, in doubles:
+// xs[m + 68] | region, where region holds the tile's skewed row windows
+// while the first column is computed (sweep_skew_doubles) and then, during
+// the sweep, win[max(m + 128, 64 PF_T, R)] | hs[256] | rowv[R] (refinement
+// only: per-row constants read once per block, kept out of registers).  xs
+// holds the first column's window, then the top row's centred window; win
+// holds the T segment of the current block.
+__host__ __device__ constexpr int sweep_xs_doubles(int m) { return (m + 68 + 3) & ~3; }
+__host__ __device__ constexpr int sweep_skew_doubles(int m, int R)
+{
+    return R == 128 ? start_rows<2>(m) + start_rows<2>(m) / 2 + 4
+         : R == 256 ? start_rows<4>(m) + start_rows<4>(m) / 4 + 4
+                    : start_rows<8>(m) + start_rows<8>(m) / 8 + 4;
+}
 __host__ __device__ constexpr int sweep_win_doubles(int m, int R)
 {
     return (m + 128 > 64 * PF_T) ? (m + 128 > R ? m + 128 : R) : (64 * PF_T > R ? 64 * PF_T : R);
 }
 __host__ __device__ constexpr int sweep_hs_offset(int m, int R)
 {
-    return (sweep_area_doubles(m, R) + sweep_win_doubles(m, R) + 3) & ~3;
+    return (sweep_xs_doubles(m) + sweep_win_doubles(m, R) + 3) & ~3;
 }
 __host__ __device__ constexpr int sweep_rowv_offset(int m, int R) { return sweep_hs_offset(m, R) + 256; }
 __host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, bool rowv)
 {
-    return (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0));
+    return (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0)) >
+                   (size_t)(sweep_xs_doubles(m) + sweep_skew_doubles(m, R))
+               ? (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0))
+               : (size_t)(sweep_xs_doubles(m) + sweep_skew_doubles(m, R));
 }
 
 // Staging of one block of 64 columns, software-pipelined: prefetch() issues
@@ -820,7 +873,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + sweep_area_doubles(m, R);
+    double* ys = lds + sweep_xs_doubles(m);  // win; the skewed rows before the sweep
     H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     F C[Q];
@@ -1040,7 +1093,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         if (all == ~0ull) return;
     }
     double* xs = lds;
-    double* ys = lds + sweep_area_doubles(m, R);
+    double* ys = lds + sweep_xs_doubles(m);  // win; the skewed rows before the sweep
     H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     double C[Q];
