@@ -68,6 +68,8 @@ struct Ctrl {
     int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
     uint32_t nhot;     // entries of SeriesDev::hot (set by k_round_end)
     int32_t hot_r;     // tile height the hot list was built for
+    int32_t exact_ref; // 1: refinement sweeps both sides of every tile (set by k_round_end)
+    int32_t band_over; // 1: more rows than KP_MAX may hold the k best exact values
     // work lists of the current round (built by k_tiles, read by the queued passes)
     alignas(128) uint32_t nlive_sel, maxc_sel;  // live selection tiles, most chunks of one tile
     uint32_t nlive_ref, maxc_ref;
@@ -102,6 +104,7 @@ struct SeriesDev {
     double* inv64;
     unsigned long long* alive;   // bitmap [nwords]
     unsigned long long* rho;     // ordered-bits row max correlation [Npad]
+    unsigned long long* rhs;     // ordered-bits row max of the selection sweep (right side) [Npad]
     int32_t* tsel;       // live selection tiles
     int32_t* tref;       // live refinement tiles
     int32_t* hot;        // tiles holding survivors after the last round, ascending [HOT_MAX]
@@ -124,7 +127,7 @@ struct SeriesDev {
 struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
-    size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho,
+    size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho, off_rhs,
         off_tsel, off_tref, off_hot, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);

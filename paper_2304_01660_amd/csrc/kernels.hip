@@ -203,6 +203,7 @@ __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
     c->nsurv = 0;
     c->ncand = 0;
     c->live_ref = 0;
+    c->band_over = 0;
     if (c->new_len) {
         c->flat_min = 0x7fffffffffffffffll;
         c->flat_max = -1;
@@ -364,7 +365,10 @@ __global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
         else if (lo < N) bits = (1ull << (N - lo)) - 1ull;
         s.alive[i] = bits;
     }
-    if (i < s.Npad) s.rho[i] = 0x000fffffffffffffull;  // ordered bits of -inf
+    if (i < s.Npad) {
+        s.rho[i] = 0x000fffffffffffffull;  // ordered bits of -inf
+        s.rhs[i] = 0x000fffffffffffffull;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -379,6 +383,7 @@ struct SweepArgs {
     const F* __restrict__ inv;
     unsigned long long* alive;
     unsigned long long* rho;
+    unsigned long long* rhs;
     Ctrl* ctrl;
     int64_t N;
     int32_t m;
@@ -939,6 +944,17 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         j = jn;
         go = sync_rows_with<Q>(A.alive, rbase, word, dm);
     }
+    // rows still alive: their largest correlation over this item's columns
+    // (rho - thr = margin * inv_i), for the refinement that sweeps only the
+    // left side of tiles whose rows are all clearly below the threshold
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t i = rbase + q;
+        if (!((dm[q] >> lane) & 1ull) && i < N && rm[q] > -f_inf<F>()) {
+            const double rt = (double)rm[q] * (double)A.inv[i] + (double)thr;
+            atomicMax(&A.rhs[i], ord_of(rt));
+        }
+    }
     evals += ev;
 }
 
@@ -962,6 +978,7 @@ __device__ __forceinline__ SweepArgs<float> args_of<float>(const SeriesDev& s, C
     A.inv = s.inv32;
     A.alive = s.alive;
     A.rho = s.rho;
+    A.rhs = s.rhs;
     A.ctrl = c;
     A.m = c->m;
     A.N = s.n - A.m + 1;
@@ -978,6 +995,7 @@ __device__ __forceinline__ SweepArgs<double> args_of<double>(const SeriesDev& s,
     A.inv = s.inv64;
     A.alive = s.alive;
     A.rho = s.rho;
+    A.rhs = s.rhs;
     A.ctrl = c;
     A.m = c->m;
     A.N = s.n - A.m + 1;
@@ -1242,7 +1260,8 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
 // from each series' counter; a workgroup drains the series in rotated order.
 template <typename F, int Q>
 __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
-                                                                        int near_cols, int chunk)
+                                                                        int near_cols, int chunk,
+                                                                        int near_rows)
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
@@ -1266,7 +1285,9 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
             const unsigned long long cc = it / nlive;
             const unsigned int p = (unsigned int)(it % nlive);
             const int64_t i0 = (int64_t)tiles[p] * R;
-            const int64_t jbeg = i0 + A.m + near_cols + (int64_t)cc * chunk;
+            // continue where the first pass (tiles of near_rows rows) ended,
+            // so that every row's right side is covered completely
+            const int64_t jbeg = (i0 / near_rows) * near_rows + A.m + near_cols + (int64_t)cc * chunk;
             if (jbeg >= A.N) continue;
             const int64_t jend = std::min<int64_t>(A.N, jbeg + chunk);
             sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
@@ -1280,7 +1301,7 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
 // Live-tile lists.  mode 0: selection tiles (R rows), chunks to the right
 // beyond the first pass; mode 1: refinement tiles, chunks on both sides.
 __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, int R, int mode,
-                        int near_cols, int chunk)
+                        int near_cols, int chunk, int near_rows)
 {
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
@@ -1305,19 +1326,43 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
     if (mode == 1) atomicAdd(&c->live_ref, cnt);
     const int64_t i0 = t * R;
     int64_t nch;
+    bool both = true;
     if (mode == 0) {
-        const int64_t j0 = i0 + m + near_cols;
+        // the first pass covered near_cols columns from its own tile's start
+        const int64_t j0 = (i0 / near_rows) * near_rows + m + near_cols;
         nch = j0 >= N ? 0 : (N - j0 + chunk - 1) / chunk;
     } else {
         const int64_t lend = std::min<int64_t>(N, i0 + R - m);
         const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
         const int64_t jr = i0 + m;
         const int64_t nr = jr < N ? (N - jr + chunk - 1) / chunk : 0;
-        nch = nl + nr;
+        // The selection sweep covered the right side of every live row in
+        // FP32; a row's exact maximum there is within the guard g of the
+        // recorded one, so the right side needs the exact sweep only when
+        // some live row's recorded maximum is above thr64 - g (or when there
+        // was no selection sweep, or the round is an exact repeat, or a bare
+        // range search, which reports every survivor's exact maximum).
+        both = !c->prune || c->exact_ref || c->mode == 3;
+        if (!both) {
+            const unsigned long long lim = ord_of(c->thr64 - (c->thr_sel - c->thr64));
+            for (int w = 0; w < words && !both; ++w) {
+                unsigned long long v = s.alive[t * words + w];
+                while (v) {
+                    const int bpos = __ffsll((long long)v) - 1;
+                    v &= v - 1ull;
+                    if (s.rhs[(t * words + w) * 64 + bpos] > lim) {
+                        both = true;
+                        break;
+                    }
+                }
+            }
+        }
+        nch = nl + (both ? nr : 0);
     }
     if (nch <= 0) return;
     const unsigned int slot = atomicAdd(mode == 0 ? &c->nlive_sel : &c->nlive_ref, 1u);
-    (mode == 0 ? s.tsel : s.tref)[slot] = (int32_t)t;
+    // refinement entries carry bit 31 when only the left side is swept
+    (mode == 0 ? s.tsel : s.tref)[slot] = both ? (int32_t)t : (int32_t)((uint32_t)t | 0x80000000u);
     atomicMax(mode == 0 ? &c->maxc_sel : &c->maxc_ref, (unsigned int)nch);
 }
 
@@ -1349,11 +1394,12 @@ __global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_refine(SeriesDev* S, i
             if (it >= total) break;
             const unsigned long long cc = it / nlive;
             const unsigned int p = (unsigned int)(it % nlive);
-            const int64_t i0 = (int64_t)tiles[p] * R;
+            const int32_t e = tiles[p];
+            const int64_t i0 = (int64_t)(e & 0x7fffffff) * R;
             const int64_t lend = std::min<int64_t>(A.N, i0 + R - A.m);
             const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
             const int64_t jr = i0 + A.m;
-            const int64_t nr = jr < A.N ? (A.N - jr + chunk - 1) / chunk : 0;
+            const int64_t nr = (e >= 0 && jr < A.N) ? (A.N - jr + chunk - 1) / chunk : 0;
             if ((int64_t)cc >= nl + nr) continue;
             const int64_t mn = std::min(nl, nr);
             bool left;
@@ -1419,6 +1465,8 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
     __shared__ unsigned int cnt_s[NW];
     __shared__ long long cand_s[KP_MAX];
     __shared__ unsigned int nc_s;
+    __shared__ unsigned long long kth_s;
+    __shared__ int kp_s;
     const SeriesDev& s = S[blockIdx.x];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
@@ -1428,7 +1476,15 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
     const int64_t nw = (N + 63) / 64;
     const unsigned long long* __restrict__ alive = s.alive;
     const unsigned long long* __restrict__ rho = s.rho;
+    const unsigned long long* __restrict__ rhs = s.rhs;
     const int k = s.k;
+    // ranking key of a live row: its refined maximum, or, where refinement
+    // swept only the left side, the larger of that and the selection sweep's
+    // (within the guard of exact); an exact repeat ranks by exact values
+    const bool exact = c->exact_ref || !c->prune || c->mode == 3;
+    auto key_of = [&](long long i) -> unsigned long long {
+        return exact ? rho[i] : (rho[i] > rhs[i] ? rho[i] : rhs[i]);
+    };
     int kp;
     if (direct_round(c)) {
         if (tid == 0) nc_s = 0;
@@ -1484,7 +1540,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
                         const int t = __ffsll((long long)bits) - 1;
                         bits &= bits - 1ull;
                         const long long i = q * 64 + t;
-                        const Key x = {rho[i], i};
+                        const Key x = {key_of(i), i};
                         if (r > 0 && !key_less(last, x)) continue;
                         if (key_less(x, best)) best = x;
                     }
@@ -1520,10 +1576,64 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
                 if (lane == 0) {
                     cand_s[r] = best.i;
                     s.cand[r] = best.i;
+                    if (r == k - 1) kth_s = best.u;
                 }
                 last = best;
             }
         }
+        if (tid == 0) kp_s = kp;
+        __syncthreads();
+        if (!exact) {
+            // Every row whose key is within 2g of the k-th smallest may hold
+            // one of the k smallest exact values (keys are within g of
+            // exact): all of them are polished, up to KP_MAX; beyond that
+            // the round is repeated with exact refinement.
+            const double g = c->thr_sel - c->thr64;
+            const unsigned long long ub = ord_of(dbl_of(kth_s) + 2.0 * g);
+            if (tid == 0) nc_s = 0;
+            __syncthreads();
+            unsigned int nb = 0;
+            for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
+                unsigned long long bits = alive[q];
+                while (bits) {
+                    const int t = __ffsll((long long)bits) - 1;
+                    bits &= bits - 1ull;
+                    nb += key_of(q * 64 + t) <= ub ? 1u : 0u;
+                }
+            }
+            if (nb) atomicAdd(&nc_s, nb);
+            __syncthreads();
+            const unsigned int nband = nc_s;
+            __syncthreads();
+            if (nband > (unsigned int)KP_MAX) {
+                if (tid == 0) {
+                    c->band_over = 1;
+                    c->nsurv = ns;
+                    c->ncand = 0;
+                }
+                return;
+            }
+            if (nband > (unsigned int)kp) {
+                if (tid == 0) nc_s = 0;
+                __syncthreads();
+                for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
+                    unsigned long long bits = alive[q];
+                    while (bits) {
+                        const int t = __ffsll((long long)bits) - 1;
+                        bits &= bits - 1ull;
+                        const long long i = q * 64 + t;
+                        if (key_of(i) <= ub) {
+                            const unsigned int slot = atomicAdd(&nc_s, 1u);
+                            cand_s[slot] = i;
+                            s.cand[slot] = i;
+                        }
+                    }
+                }
+                if (tid == 0) kp_s = (int)nband;
+                __syncthreads();
+            }
+        }
+        kp = kp_s;
         if (tid == 0) {
             c->nsurv = ns;
             c->ncand = (unsigned int)kp;
@@ -1721,20 +1831,25 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
     const bool direct = direct_round(c);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (kp >= k) {
+        // eight threads per candidate (all candidates at once): strided
+        // partials, then a reduction over the eight
         const int64_t npart = s.npart;
         const int64_t nblk = (s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS;
-        for (int cid = w; cid < kp; cid += END_BLOCK / 64) {
+        const int sub = tid & 7;
+        for (int cid = tid >> 3; cid < kp; cid += END_BLOCK / 8) {
             double best = -f_inf<double>(), bj = 1e300;
-            for (int64_t p = lane; p < nblk; p += 64) {
-                const double v = s.part[((int64_t)cid * npart + p) * 2];
-                const double jj = s.part[((int64_t)cid * npart + p) * 2 + 1];
+            const double* pc = s.part + (int64_t)cid * npart * 2;
+#pragma unroll 4
+            for (int64_t p = sub; p < nblk; p += 8) {
+                const double v = pc[p * 2];
+                const double jj = pc[p * 2 + 1];
                 if (v > best || (v == best && jj < bj)) {
                     best = v;
                     bj = jj;
                 }
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
+            for (int o = 4; o >= 1; o >>= 1) {
                 const double v = __shfl_xor(best, o);
                 const double jj = __shfl_xor(bj, o);
                 if (v > best || (v == best && jj < bj)) {
@@ -1742,7 +1857,7 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
                     bj = jj;
                 }
             }
-            if (lane == 0) {
+            if (sub == 0) {
                 const double d2 = 2.0 * (double)m * (1.0 - best);
                 const long long i = s.cand[cid];
                 nn_s[cid] = sqrt(fmin(4.0 * (double)m, fmax(0.0, d2)));
@@ -1768,7 +1883,10 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
     }
     __syncthreads();
     const unsigned int ns = direct ? (kp >= k ? nvalid_s : (unsigned int)kp) : c->nsurv;
-    const bool ok = ns >= (unsigned int)k && kp >= k;
+    // the candidates could not be narrowed to KP_MAX: same r again, with both
+    // sides of every tile refined exactly
+    const bool redo = c->band_over != 0;
+    const bool ok = ns >= (unsigned int)k && kp >= k && !redo;
     if (ok && tid < kp && valid_s[tid]) {
         int rank = 0;
         for (int q = 0; q < kp; ++q)
@@ -1790,15 +1908,18 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
     if (tid == 0) {
         c->rounds += 1;
         c->nsurv = ns;
+        c->exact_ref = redo ? 1 : 0;
         if (ok) {
             c->done = 1;
             c->survivors += ns;
             if (s.count) s.count[li] = (int32_t)ns;
-        } else {
+        } else if (!redo) {
             c->done = 0;
             if (c->mode == 0) c->r *= 0.5;
             else if (c->mode == 1) c->r *= 0.99;
             else if (c->mode == 2) c->r = (c->step > 0.0) ? c->r - c->step : 0.99 * c->r;
+        } else {
+            c->done = 0;
         }
         if (!(c->done && c->m >= s.maxL)) atomicAdd(&rem[0], 1);
     }
@@ -1863,10 +1984,10 @@ static void launch_far(const Batch& bt, const SweepCfg& cfg, const int64_t* tota
 {
     const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, false);
     hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TSEL]), dim3(256), 0, st, bt.s, bt.B,
-                       bt.pfx[PFX_TSEL], 64 * Q, 0, cfg.near_cols, cfg.chunk_cols);
+                       bt.pfx[PFX_TSEL], 64 * Q, 0, cfg.near_cols, cfg.chunk_cols, 64 * cfg.q_near);
     cfg.timer->begin(1, st);
     hipLaunchKernelGGL((k_select_far<F, Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
-                       cfg.near_cols, cfg.chunk_cols);
+                       cfg.near_cols, cfg.chunk_cols, 64 * cfg.q_near);
     cfg.timer->end(1, st);
 }
 
@@ -1874,7 +1995,7 @@ template <int Q>
 static void launch_refine(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
     hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TREF]), dim3(256), 0, st, bt.s, bt.B,
-                       bt.pfx[PFX_TREF], 64 * Q, 1, 0, cfg.chunk_cols);
+                       bt.pfx[PFX_TREF], 64 * Q, 1, 0, cfg.chunk_cols, 64 * cfg.q_near);
     const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, true);
     cfg.timer->begin(2, st);
     hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
@@ -2082,6 +2203,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_h64 = o;   o = al256(o + 3 * al256(sizeof(double) * hl));
     l.off_alive = o; o = al256(o + sizeof(unsigned long long) * (size_t)l.nwords);
     l.off_rho = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
+    l.off_rhs = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
     l.off_tsel = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_tref = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_hot = o;   o = al256(o + sizeof(int32_t) * (size_t)HOT_MAX);
@@ -2126,6 +2248,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.inv64 = (double*)(p + l.off_h64 + 2 * al256(sizeof(double) * hl));
     s.alive = (unsigned long long*)(p + l.off_alive);
     s.rho = (unsigned long long*)(p + l.off_rho);
+    s.rhs = (unsigned long long*)(p + l.off_rhs);
     s.tsel = (int32_t*)(p + l.off_tsel);
     s.tref = (int32_t*)(p + l.off_tref);
     s.hot = (int32_t*)(p + l.off_hot);
