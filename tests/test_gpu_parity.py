@@ -129,6 +129,29 @@ def test_tile_heights_match_bruteforce(dist_bits, rows):
         _check_against_profiles(T, out, minL, maxL, k)
 
 
+@pytest.mark.parametrize("dist_bits", [64, 32])
+def test_wide_guard_band_repeats_rounds_exactly(dist_bits):
+    """A wide guard band leaves more rows within twice the guard of the k-th
+    ranking key than the exact pass takes: those rounds are repeated with
+    both sides refined exactly, and the results stay those of brute force."""
+    dev = _dev()
+    api = _api()
+    repeated = 0
+    cases = [(0, "noise", 3000, 20, 22, 3), (1, "rw", 2500, 30, 31, 1), (2, "ecg", 3200, 40, 41, 2)]
+    for c, kind, n, minL, maxL, k in cases:
+        T = synth.small_random(8100 + c, n, kind)
+        _say("wide-guard", dist_bits, c, kind, n, minL, maxL, k)
+        ref = api.discords(torch.from_numpy(T).to(dev), minL, maxL, k, dist_bits=dist_bits,
+                           return_stats=True)
+        out = api.discords(torch.from_numpy(T).to(dev), minL, maxL, k, dist_bits=dist_bits,
+                           guard=0.9, return_stats=True)
+        _check_against_profiles(T, out, minL, maxL, k)
+        _say("rounds", ref["stats"]["range_searches"], out["stats"]["range_searches"])
+        repeated += out["stats"]["range_searches"] > ref["stats"]["range_searches"]
+    if dist_bits == 32:  # the FP32 sweep's wider keys overflow the band on these series
+        assert repeated > 0
+
+
 def test_config1_matches_golden():
     dev = _dev()
     api = _api()
