@@ -30,9 +30,11 @@ constexpr int MAX_ATTEMPTS = 5000;
 // A round whose selection leaves at most this many live subsequences skips
 // the refinement sweep: the exact pass evaluates all of them directly.
 constexpr int DIRECT_MAX = KP_MAX;
-// Row tiles that held survivors at the end of a round (at most HOT_MAX of
-// them) lead the next round's first selection pass.
+// Row tiles that held survivors at the end of a round, or whose first-pass
+// items swept at least 1/HOT_FRAC of the series' columns in all, lead the
+// next round's first selection pass (at most HOT_MAX of them).
 constexpr int HOT_MAX = 64;
+constexpr int HOT_FRAC = 8;
 
 // Pair-evaluation counters: EV_SLOTS slots per class, so that the many
 // work items of a launch add to different addresses.
@@ -107,7 +109,8 @@ struct SeriesDev {
     unsigned long long* rhs;     // ordered-bits row max of the selection sweep (right side) [Npad]
     int32_t* tsel;       // live selection tiles
     int32_t* tref;       // live refinement tiles
-    int32_t* hot;        // tiles holding survivors after the last round, ascending [HOT_MAX]
+    int32_t* hot;        // hot tiles of the last round, ascending [HOT_MAX]
+    uint32_t* twork;     // 64-column blocks swept by each first-pass tile this round [nwords]
     int64_t* cand;       // polished candidates [KP_MAX]
     double* part;        // polish partials [KP_MAX * npart * 2 + tail]
     double* xc;          // centred candidate windows [KP_MAX][maxL + 8], then their sums
@@ -128,7 +131,7 @@ struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
     size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho, off_rhs,
-        off_tsel, off_tref, off_hot, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
+        off_tsel, off_tref, off_hot, off_twork, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
 SeriesDev carve(void* base, const Layout& lay);

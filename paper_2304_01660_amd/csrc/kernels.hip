@@ -384,6 +384,7 @@ struct SweepArgs {
     unsigned long long* alive;
     unsigned long long* rho;
     unsigned long long* rhs;
+    uint32_t* twork;
     Ctrl* ctrl;
     int64_t N;
     int32_t m;
@@ -858,7 +859,7 @@ __device__ __forceinline__ void sel_block_full(F (&C)[Q], const F (&a)[Q], const
 
 template <typename F, int Q>
 __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_t jend, F thr,
-                         double* lds, unsigned long long& evals)
+                         double* lds, unsigned long long& evals, uint32_t* work)
 {
     constexpr int R = 64 * Q;
     i0 = uniform_i64(i0);
@@ -920,6 +921,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     }
     unsigned long long ev = pair_count(i0, std::min<int64_t>(i0 + R, N), jbeg, 1, m, false);
     bool go = sync_rows<Q>(A.alive, rbase, dm);
+    uint32_t nblk = 0;
     int64_t j = jbeg + 1;
     Prefetch<F> pf;
     if (go && j < jend) prefetch<F>(pf, A.T, A.mu, A.df, A.dg, A.inv, j);
@@ -943,7 +945,9 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, false);
         j = jn;
         go = sync_rows_with<Q>(A.alive, rbase, word, dm);
+        ++nblk;
     }
+    if (work && lane == 0 && nblk) atomicAdd(work, nblk);
     // rows still alive: their largest correlation over this item's columns
     // (rho - thr = margin * inv_i), for the refinement that sweeps only the
     // left side of tiles whose rows are all clearly below the threshold
@@ -979,6 +983,7 @@ __device__ __forceinline__ SweepArgs<float> args_of<float>(const SeriesDev& s, C
     A.alive = s.alive;
     A.rho = s.rho;
     A.rhs = s.rhs;
+    A.twork = s.twork;
     A.ctrl = c;
     A.m = c->m;
     A.N = s.n - A.m + 1;
@@ -996,6 +1001,7 @@ __device__ __forceinline__ SweepArgs<double> args_of<double>(const SeriesDev& s,
     A.alive = s.alive;
     A.rho = s.rho;
     A.rhs = s.rhs;
+    A.twork = s.twork;
     A.ctrl = c;
     A.m = c->m;
     A.N = s.n - A.m + 1;
@@ -1250,7 +1256,7 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
     const int64_t jend = std::min<int64_t>(std::min<int64_t>(A.N, jbeg + chunk), j00 + near_cols);
     const F thr = sel_threshold<F>(c);
     unsigned long long ev = 0;
-    sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
+    sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev, &A.twork[tile]);
     if (threadIdx.x == 0 && ev) {
         atomicAdd(&s.evc[EV_NEAR * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
     }
@@ -1290,7 +1296,7 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
             const int64_t jbeg = (i0 / near_rows) * near_rows + A.m + near_cols + (int64_t)cc * chunk;
             if (jbeg >= A.N) continue;
             const int64_t jend = std::min<int64_t>(A.N, jbeg + chunk);
-            sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev);
+            sel_item<F, Q>(A, i0, jbeg, jend, thr, lds, ev, nullptr);
         }
         if (threadIdx.x == 0 && ev) {
             atomicAdd(&s.evc[EV_FAR * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
@@ -1923,17 +1929,21 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
         }
         if (!(c->done && c->m >= s.maxL)) atomicAdd(&rem[0], 1);
     }
-    // Tiles of hot_rows rows that still hold survivors, in ascending order
-    // (the first HOT_MAX of them): the next round's first selection pass
-    // dispatches all their chunks before any other tile's, so that the
-    // longest work items of the pass start first.
+    // Hot tiles of hot_rows rows, in ascending order (the first HOT_MAX of
+    // them): those that still hold survivors or whose first-pass items swept
+    // at least N / HOT_FRAC columns this round.  The next round's first
+    // selection pass dispatches all their chunks before any other tile's, so
+    // that the longest work items of the pass start first.  The per-tile
+    // work counters restart.
     __shared__ unsigned int wcnt_s[END_BLOCK / 64];
     __shared__ unsigned int base_s;
-    __threadfence();
+    // (the bitmap atomics of this block completed before the barrier; the
+    // scan reads the bitmap with agent-scope loads)
     __syncthreads();
     if (tid == 0) base_s = 0;
     const int64_t ntl = (s.n - m + 1 + hot_rows - 1) / hot_rows;
     const int wpt = hot_rows / 64;
+    const uint32_t hot_work = (uint32_t)((s.n - m + 1 + 64 * HOT_FRAC - 1) / (64 * HOT_FRAC));
     for (int64_t t0 = 0; t0 < ntl; t0 += END_BLOCK) {
         __syncthreads();
         const unsigned int base = base_s;
@@ -1942,7 +1952,8 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
         if (t < ntl) {
             unsigned long long any = 0ull;
             for (int w2 = 0; w2 < wpt; ++w2) any |= load_word(&s.alive[t * wpt + w2]);
-            hot = any != 0ull;
+            hot = any != 0ull || s.twork[t] >= hot_work;
+            s.twork[t] = 0u;
         }
         const unsigned long long bal = __ballot(hot);
         if (lane == 0) wcnt_s[w] = (unsigned int)__popcll(bal);
@@ -2207,6 +2218,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_tsel = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_tref = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_hot = o;   o = al256(o + sizeof(int32_t) * (size_t)HOT_MAX);
+    l.off_twork = o; o = al256(o + sizeof(uint32_t) * (size_t)l.nwords);
     l.off_cand = o;  o = al256(o + sizeof(int64_t) * (size_t)KP_MAX);
     l.off_part = o;  o = al256(o + sizeof(double) * (size_t)(2 * KP_MAX * (l.npart + 1)));
     l.off_xc = o;    o = al256(o + sizeof(double) * (size_t)KP_MAX * (size_t)(maxL + 9));
@@ -2252,6 +2264,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.tsel = (int32_t*)(p + l.off_tsel);
     s.tref = (int32_t*)(p + l.off_tref);
     s.hot = (int32_t*)(p + l.off_hot);
+    s.twork = (uint32_t*)(p + l.off_twork);
     s.cand = (int64_t*)(p + l.off_cand);
     s.part = (double*)(p + l.off_part);
     s.xc = (double*)(p + l.off_xc);

@@ -46,7 +46,10 @@ __global__ void k_ctrl_init(SeriesDev* S)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = g; i < s.L; i += stride) s.hist[i] = 0.0;
     for (int64_t i = g; i < EV_CLASSES * EV_SLOTS; i += stride) s.evc[i] = 0ull;
-    for (int64_t w = g; w < s.nwords; w += stride) s.alive[w] = 0ull;
+    for (int64_t w = g; w < s.nwords; w += stride) {
+        s.alive[w] = 0ull;
+        s.twork[w] = 0u;
+    }
 }
 
 __global__ void k_copy_sum(SeriesDev* S)
