@@ -21,9 +21,7 @@ constexpr int R_MAX = 512;   // tallest row tile (64 lanes x 8 rows)
 constexpr int KP_EXTRA = 4;  // candidates polished beyond k
 constexpr int K_MAX = 64;
 constexpr int KP_MAX = K_MAX + KP_EXTRA;
-constexpr int POLISH_BLOCK = 128;
-constexpr int POLISH_CPT = 4;  // columns per polish thread
-constexpr int POLISH_COLS = POLISH_BLOCK * POLISH_CPT;
+constexpr int POLISH_COLS = 512;  // columns per exact-pass block (one partial each)
 constexpr int TOPK_BLOCK = 1024;
 constexpr int RED_BLOCKS = 256;   // series reductions: blocks of 256 threads
 constexpr int MAX_ATTEMPTS = 5000;

@@ -1665,154 +1665,155 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
 
 // Exact FP64 nearest-neighbour correlation of the candidate rows against
 // every column: direct centred dot products (no recurrence), the reference
-// the reported distances and neighbour indices come from.  A block owns
-// POLISH_COLS consecutive columns of one series (POLISH_CPT per thread,
-// POLISH_BLOCK apart, so LDS reads are conflict free) for one group of
-// POLISH_G candidates (grid.y), and stages the columns' values in LDS.  The
-// candidates' centred windows pass through LDS in chunks of POLISH_KC, so
-// per window offset k a thread does POLISH_CPT + POLISH_G LDS reads (the
-// candidate values are broadcasts) for POLISH_G x POLISH_CPT FMAs.  One
-// (max rho, argmax j) partial per candidate.
-constexpr int POLISH_G = 4;
-constexpr int POLISH_KC = 256;
+// the reported distances and neighbour indices come from.  It is a dense
+// contraction X (candidates x m) . H (m x columns) with H[k][j] = t_{j+k},
+// so it runs on the FP64 matrix cores: V_MFMA_F64_16X16X4F64 multiplies a
+// 16 x 4 block of candidate values by a 4 x 16 block of the series, lane l
+// supplying X[l % 16][l / 16] and H[l / 16][l % 16] and receiving
+// D[l / 16 + 4 r][l % 16], r < 4.  A block owns POLISH_COLS consecutive
+// columns of one series (PM_CT tiles of 16 per wave) for one group of PM_G
+// candidates (grid.y); the columns' values and chunks of PM_KC offsets of
+// the candidates' centred windows are staged in LDS, so a lane reads one
+// value per matrix instruction (1024 FMAs).  One (max rho, argmax j)
+// partial per candidate.
+constexpr int PM_WAVES = POLISH_COLS / 128;   // waves per block
+constexpr int PM_CT = 8;                      // 16-column tiles per wave
+constexpr int PM_G = 16;                      // candidates per block
+constexpr int PM_KC = 128;                    // window offsets per LDS chunk
+typedef double pm_acc_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(POLISH_BLOCK) void k_polish(SeriesDev* S, int B,
-                                                         const int64_t* __restrict__ pfx)
+__global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
+                                                          const int64_t* __restrict__ pfx)
 {
+    static_assert(PM_WAVES * PM_CT * 16 == POLISH_COLS, "polish block geometry");
     extern __shared__ double lds[];
-    __shared__ double red_v[POLISH_BLOCK / 64][POLISH_G];
-    __shared__ long long red_j[POLISH_BLOCK / 64][POLISH_G];
+    __shared__ double red_v[PM_WAVES][PM_G];
+    __shared__ long long red_j[PM_WAVES][PM_G];
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
     const int ncand = (int)c->ncand;
-    if ((int)blockIdx.y * POLISH_G >= ncand) return;
+    const int g0 = (int)blockIdx.y * PM_G;
+    if (g0 >= ncand) return;
     const int32_t m = c->m;
     const int64_t N = s.n - m + 1;
-    const double* __restrict__ T = s.T;
     const double* __restrict__ mu = cur_mu(s, c);
     const double* __restrict__ var = cur_var(s, c);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ca = lane & 15, ka = lane >> 4;
     const int64_t blk = blockIdx.x - pfx[b];
     const int64_t j0 = blk * POLISH_COLS;
-    double* xg = lds;                          // [POLISH_G][POLISH_KC] candidate chunk
-    double* ts = lds + POLISH_G * POLISH_KC;   // T[j0 .. j0 + POLISH_COLS + m)
-    const double feps = c->flat_eps;
-    int64_t jc[POLISH_CPT];
-    bool colok[POLISH_CPT], flat_j[POLISH_CPT];
-    double sgj[POLISH_CPT], muj[POLISH_CPT];
-#pragma unroll
-    for (int q = 0; q < POLISH_CPT; ++q) {
-        jc[q] = j0 + tid + q * POLISH_BLOCK;
-        colok[q] = jc[q] < N;
-        sgj[q] = colok[q] ? sqrt(var[jc[q]]) : 1.0;
-        muj[q] = colok[q] ? mu[jc[q]] : 0.0;
-        flat_j[q] = colok[q] && sgj[q] <= feps;
-    }
+    const int colbase = w * 16 * PM_CT;
+    double* xg = lds;                   // [PM_G][PM_KC] candidate window chunk
+    double* ts = lds + PM_G * PM_KC;    // t[j0 .. j0 + POLISH_COLS + m + 4)
     const int64_t stride = (int64_t)s.maxL + 8;
     const double* __restrict__ xc = s.xc;
-    const int w = tid >> 6;
-    unsigned long long ev = 0;
-    {
-        const int g0 = (int)blockIdx.y * POLISH_G;
-        int cidx[POLISH_G];
+    pm_acc_t acc[PM_CT];
 #pragma unroll
-        for (int g = 0; g < POLISH_G; ++g) cidx[g] = min(g0 + g, ncand - 1);
-        double acc[POLISH_G][POLISH_CPT];
+    for (int ct = 0; ct < PM_CT; ++ct) acc[ct] = (pm_acc_t){0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < m; kb += PM_KC) {
+        const int kn = min(PM_KC, m - kb);
+        __syncthreads();  // the previous chunk is consumed
+        {
+            constexpr int PER = PM_G * PM_KC / (64 * PM_WAVES);
+            double v[PER];
 #pragma unroll
-        for (int g = 0; g < POLISH_G; ++g)
-#pragma unroll
-            for (int q = 0; q < POLISH_CPT; ++q) acc[g][q] = 0.0;
-        for (int kb = 0; kb < m; kb += POLISH_KC) {
-            const int kn = min(POLISH_KC, m - kb);
-            __syncthreads();  // the previous chunk (and ts) complete / consumed
-            {
-                constexpr int PER = POLISH_G * POLISH_KC / POLISH_BLOCK;
-                double v[PER];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    const int e = tid + POLISH_BLOCK * u;
-                    const int g = e / POLISH_KC, k = e - g * POLISH_KC;
-                    v[u] = k < kn ? xc[cidx[g] * stride + kb + k] : 0.0;
-                }
-                // the columns' values travel together with the first chunk
-                if (kb == 0) lds_fill(ts, T + j0, POLISH_COLS + m);
-#pragma unroll
-                for (int u = 0; u < PER; ++u) xg[tid + POLISH_BLOCK * u] = v[u];
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + 64 * PM_WAVES * u;
+                const int g = e / PM_KC, k = e - g * PM_KC;
+                const int cid = min(g0 + g, ncand - 1);
+                v[u] = k < kn ? xc[cid * stride + kb + k] : 0.0;  // zero past m
             }
-            __syncthreads();
-            const double* tb = ts + tid + kb;
-#pragma unroll 2
-            for (int k = 0; k < kn; ++k) {
-                double tv[POLISH_CPT];
+            // the columns' values travel together with the first chunk
+            if (kb == 0) lds_fill(ts, s.T + j0, POLISH_COLS + m + 4);
 #pragma unroll
-                for (int q = 0; q < POLISH_CPT; ++q) tv[q] = tb[q * POLISH_BLOCK + k];
-#pragma unroll
-                for (int g = 0; g < POLISH_G; ++g) {
-                    const double x = xg[g * POLISH_KC + k];
-#pragma unroll
-                    for (int q = 0; q < POLISH_CPT; ++q) acc[g][q] = fma(x, tv[q], acc[g][q]);
-                }
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < POLISH_G; ++g) {
-            const int64_t i = s.cand[cidx[g]];
-            const double Sx = xc[KP_MAX * stride + cidx[g]];
-            const double sgi = sqrt(var[i]);
-            const bool flat_i = sgi <= feps;
-            double best = -f_inf<double>();
-            long long bj = 0x7fffffffffffffffll;
-#pragma unroll
-            for (int q = 0; q < POLISH_CPT; ++q) {
-                if (colok[q] && (jc[q] <= i - m || jc[q] >= i + m)) {
-                    double rh;
-                    if (flat_i || flat_j[q]) {
-                        rh = (flat_i && flat_j[q]) ? 1.0 : 0.0;
-                    } else {
-                        const double Cv = acc[g][q] - muj[q] * Sx;
-                        rh = fmin(1.0, fmax(-1.0, Cv / ((double)m * sgi * sgj[q])));
-                    }
-                    if (rh > best) {  // columns ascend with q: ties keep the smaller j
-                        best = rh;
-                        bj = jc[q];
-                    }
-                    if (g0 + g < ncand) ++ev;
-                }
-            }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double v = __shfl_xor(best, o);
-                const long long jj = __shfl_xor(bj, o);
-                if (v > best || (v == best && jj < bj)) {
-                    best = v;
-                    bj = jj;
-                }
-            }
-            if ((tid & 63) == 0) {
-                red_v[w][g] = best;
-                red_j[w][g] = bj;
-            }
+            for (int u = 0; u < PER; ++u) xg[tid + 64 * PM_WAVES * u] = v[u];
         }
         __syncthreads();
-        if (tid < POLISH_G && g0 + tid < ncand) {
-            double best = red_v[0][tid];
-            long long bj = red_j[0][tid];
-            for (int q = 1; q < POLISH_BLOCK / 64; ++q)
-                if (red_v[q][tid] > best || (red_v[q][tid] == best && red_j[q][tid] < bj)) {
-                    best = red_v[q][tid];
-                    bj = red_j[q][tid];
-                }
-            const int64_t slot = ((int64_t)(g0 + tid) * s.npart + blk) * 2;
-            s.part[slot] = best;
-            s.part[slot + 1] = (double)bj;
+        const double* xa = xg + ca * PM_KC + ka;
+        const double* tb = ts + colbase + kb + ka + ca;
+        for (int k4 = 0; k4 < kn; k4 += 4) {
+            const double av = xa[k4];
+#pragma unroll
+            for (int ct = 0; ct < PM_CT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tb[k4 + 16 * ct], acc[ct], 0, 0, 0);
         }
     }
+    // epilogue: lane holds D[ka + 4 r][16 ct + ca]
+    const double feps = c->flat_eps;
+    const double* __restrict__ sxs = xc + KP_MAX * stride;
+    int64_t ci[4];
+    double sxv[4], sgi[4], best[4];
+    bool flat_i[4];
+    long long bj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int cid = min(g0 + ka + 4 * r, ncand - 1);
+        ci[r] = s.cand[cid];
+        sxv[r] = sxs[cid];
+        sgi[r] = sqrt(var[ci[r]]);
+        flat_i[r] = sgi[r] <= feps;
+        best[r] = -f_inf<double>();
+        bj[r] = 0x7fffffffffffffffll;
+    }
+    unsigned long long ev = 0;
+#pragma unroll
+    for (int ct = 0; ct < PM_CT; ++ct) {
+        const int64_t j = j0 + colbase + 16 * ct + ca;
+        if (j >= N) continue;
+        const double sgj = sqrt(var[j]), muj = mu[j];
+        const bool flat_j = sgj <= feps;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (j <= ci[r] - m || j >= ci[r] + m) {
+                double rh;
+                if (flat_i[r] || flat_j) {
+                    rh = (flat_i[r] && flat_j) ? 1.0 : 0.0;
+                } else {
+                    const double Cv = acc[ct][r] - muj * sxv[r];
+                    rh = fmin(1.0, fmax(-1.0, Cv / ((double)m * sgi[r] * sgj)));
+                }
+                if (rh > best[r]) {  // a lane's columns ascend with ct: ties keep the smaller j
+                    best[r] = rh;
+                    bj[r] = j;
+                }
+                if (g0 + ka + 4 * r < ncand) ++ev;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {  // the 16 lanes of one candidate row
+            const double v = __shfl_xor(best[r], o);
+            const long long jj = __shfl_xor(bj[r], o);
+            if (v > best[r] || (v == best[r] && jj < bj[r])) {
+                best[r] = v;
+                bj[r] = jj;
+            }
+        }
+        if (ca == 0) {
+            red_v[w][ka + 4 * r] = best[r];
+            red_j[w][ka + 4 * r] = bj[r];
+        }
+    }
+    __syncthreads();
+    if (tid < PM_G && g0 + tid < ncand) {
+        double bv = red_v[0][tid];
+        long long bjj = red_j[0][tid];
+        for (int q = 1; q < PM_WAVES; ++q)
+            if (red_v[q][tid] > bv || (red_v[q][tid] == bv && red_j[q][tid] < bjj)) {
+                bv = red_v[q][tid];
+                bjj = red_j[q][tid];
+            }
+        const int64_t slot = ((int64_t)(g0 + tid) * s.npart + blk) * 2;
+        s.part[slot] = bv;
+        s.part[slot + 1] = (double)bjj;
+    }
     ev = (unsigned long long)wave_sum((double)ev);
-    if ((tid & 63) == 0 && ev)
-        atomicAdd(&s.evc[EV_POL * EV_SLOTS + ((blockIdx.x + blockIdx.y + (tid >> 6)) & (EV_SLOTS - 1))],
-                  ev);
+    if (lane == 0 && ev)
+        atomicAdd(&s.evc[EV_POL * EV_SLOTS + ((blockIdx.x + blockIdx.y + w) & (EV_SLOTS - 1))], ev);
 }
 
 // Close the round of every series (one block each): reduce the polish
@@ -2052,11 +2053,11 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
     default: launch_refine<2>(bt, cfg, total, st); break;
     }
     hipLaunchKernelGGL(k_select_top, dim3(bt.B), dim3(TOPK_BLOCK), 0, st, bt.s);
-    const size_t lds = sizeof(double) * (size_t)(POLISH_G * POLISH_KC + POLISH_COLS + bt.maxL_all);
+    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_KC + POLISH_COLS + bt.maxL_all + 4);
     cfg.timer->begin(3, st);
     hipLaunchKernelGGL(k_polish,
-                       dim3((unsigned int)total[PFX_POLISH], (KP_MAX + POLISH_G - 1) / POLISH_G),
-                       dim3(POLISH_BLOCK), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
+                       dim3((unsigned int)total[PFX_POLISH], (KP_MAX + PM_G - 1) / PM_G),
+                       dim3(64 * PM_WAVES), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
     cfg.timer->end(3, st);
     hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining,
                        64 * cfg.q_near);
