@@ -105,6 +105,7 @@ struct SeriesDev {
     unsigned long long* alive;   // bitmap [nwords]
     unsigned long long* rho;     // ordered-bits row max correlation [Npad]
     unsigned long long* rhs;     // ordered-bits row max of the selection sweep (right side) [Npad]
+    unsigned long long* unc;     // bitmap [nwords]: rows whose rhs is above thr64 - guard
     int32_t* tsel;       // live selection tiles
     int32_t* tref;       // live refinement tiles
     int32_t* hot;        // hot tiles of the last round, ascending [HOT_MAX]
@@ -128,7 +129,7 @@ struct SeriesDev {
 struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
-    size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho, off_rhs,
+    size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho, off_rhs, off_unc,
         off_tsel, off_tref, off_hot, off_twork, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);

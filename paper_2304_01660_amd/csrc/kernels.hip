@@ -364,6 +364,7 @@ __global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
         if (lo + 64 <= N) bits = ~0ull;
         else if (lo < N) bits = (1ull << (N - lo)) - 1ull;
         s.alive[i] = bits;
+        s.unc[i] = 0ull;
     }
     if (i < s.Npad) {
         s.rho[i] = 0x000fffffffffffffull;  // ordered bits of -inf
@@ -384,6 +385,7 @@ struct SweepArgs {
     unsigned long long* alive;
     unsigned long long* rho;
     unsigned long long* rhs;
+    unsigned long long* unc;
     uint32_t* twork;
     Ctrl* ctrl;
     int64_t N;
@@ -950,13 +952,39 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     if (work && lane == 0 && nblk) atomicAdd(work, nblk);
     // rows still alive: their largest correlation over this item's columns
     // (rho - thr = margin * inv_i), for the refinement that sweeps only the
-    // left side of tiles whose rows are all clearly below the threshold
+    // left side of tiles whose rows are all clearly below the threshold;
+    // rows above thr64 - guard are marked in unc
+    const double ulim = 2.0 * A.ctrl->thr64 - A.ctrl->thr_sel;
+    unsigned long long ub[Q];
+    unsigned long long uany = 0ull;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int64_t i = rbase + q;
+        bool u = false;
         if (!((dm[q] >> lane) & 1ull) && i < N && rm[q] > -f_inf<F>()) {
             const double rt = (double)rm[q] * (double)A.inv[i] + (double)thr;
             atomicMax(&A.rhs[i], ord_of(rt));
+            u = rt > ulim;
+        }
+        ub[q] = uniform64(__ballot(u));
+        uany |= ub[q];
+    }
+    // one atomic per bitmap word: lane l's slot q is row Q l + q of the tile
+    if (uany != 0ull && lane == 0) {
+        constexpr int LPW = 64 / Q;  // lanes per bitmap word
+#pragma unroll
+        for (int wd = 0; wd < Q; ++wd) {
+            unsigned long long mask = 0ull;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                unsigned long long lb = (ub[q] >> (wd * LPW)) & ((LPW == 64) ? ~0ull : ((1ull << LPW) - 1ull));
+                while (lb) {
+                    const int l = __ffsll((long long)lb) - 1;
+                    lb &= lb - 1ull;
+                    mask |= 1ull << (Q * l + q);
+                }
+            }
+            if (mask) atomicOr(&A.unc[(i0 >> 6) + wd], mask);
         }
     }
     evals += ev;
@@ -983,6 +1011,7 @@ __device__ __forceinline__ SweepArgs<float> args_of<float>(const SeriesDev& s, C
     A.alive = s.alive;
     A.rho = s.rho;
     A.rhs = s.rhs;
+    A.unc = s.unc;
     A.twork = s.twork;
     A.ctrl = c;
     A.m = c->m;
@@ -1001,6 +1030,7 @@ __device__ __forceinline__ SweepArgs<double> args_of<double>(const SeriesDev& s,
     A.alive = s.alive;
     A.rho = s.rho;
     A.rhs = s.rhs;
+    A.unc = s.unc;
     A.twork = s.twork;
     A.ctrl = c;
     A.m = c->m;
@@ -1350,18 +1380,9 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
         // range search, which reports every survivor's exact maximum).
         both = !c->prune || c->exact_ref || c->mode == 3;
         if (!both) {
-            const unsigned long long lim = ord_of(c->thr64 - (c->thr_sel - c->thr64));
-            for (int w = 0; w < words && !both; ++w) {
-                unsigned long long v = s.alive[t * words + w];
-                while (v) {
-                    const int bpos = __ffsll((long long)v) - 1;
-                    v &= v - 1ull;
-                    if (s.rhs[(t * words + w) * 64 + bpos] > lim) {
-                        both = true;
-                        break;
-                    }
-                }
-            }
+            unsigned long long u = 0ull;
+            for (int w = 0; w < words; ++w) u |= s.alive[t * words + w] & s.unc[t * words + w];
+            both = u != 0ull;
         }
         nch = nl + (both ? nr : 0);
     }
@@ -1838,25 +1859,35 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
     const bool direct = direct_round(c);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (kp >= k) {
-        // eight threads per candidate (all candidates at once): strided
-        // partials, then a reduction over the eight
+        // tpc threads per candidate (all candidates at once, tpc as large as
+        // the block allows, at most a wave): strided partials loaded eight at
+        // a time before they are compared (they come from other XCDs' caches,
+        // so each batch costs a full memory latency), then a reduction over
+        // the tpc threads
         const int64_t npart = s.npart;
         const int64_t nblk = (s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS;
-        const int sub = tid & 7;
-        for (int cid = tid >> 3; cid < kp; cid += END_BLOCK / 8) {
+        int tpc = 64;
+        while (tpc > 1 && tpc * kp > END_BLOCK) tpc >>= 1;
+        const int sub = tid & (tpc - 1);
+        for (int cid = tid / tpc; cid < kp; cid += END_BLOCK / tpc) {
             double best = -f_inf<double>(), bj = 1e300;
             const double* pc = s.part + (int64_t)cid * npart * 2;
-#pragma unroll 4
-            for (int64_t p = sub; p < nblk; p += 8) {
-                const double v = pc[p * 2];
-                const double jj = pc[p * 2 + 1];
-                if (v > best || (v == best && jj < bj)) {
-                    best = v;
-                    bj = jj;
-                }
-            }
+            for (int64_t p0 = sub; p0 < nblk; p0 += 8 * (int64_t)tpc) {
+                double v[8], jj[8];
 #pragma unroll
-            for (int o = 4; o >= 1; o >>= 1) {
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t p = p0 + (int64_t)u * tpc;
+                    v[u] = p < nblk ? pc[p * 2] : -f_inf<double>();
+                    jj[u] = p < nblk ? pc[p * 2 + 1] : 1e300;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (v[u] > best || (v[u] == best && jj[u] < bj)) {
+                        best = v[u];
+                        bj = jj[u];
+                    }
+            }
+            for (int o = tpc >> 1; o >= 1; o >>= 1) {
                 const double v = __shfl_xor(best, o);
                 const double jj = __shfl_xor(bj, o);
                 if (v > best || (v == best && jj < bj)) {
@@ -2216,6 +2247,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_alive = o; o = al256(o + sizeof(unsigned long long) * (size_t)l.nwords);
     l.off_rho = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
     l.off_rhs = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.Npad);
+    l.off_unc = o;   o = al256(o + sizeof(unsigned long long) * (size_t)l.nwords);
     l.off_tsel = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_tref = o;  o = al256(o + sizeof(int32_t) * (size_t)(l.Npad / 64 + 1));
     l.off_hot = o;   o = al256(o + sizeof(int32_t) * (size_t)HOT_MAX);
@@ -2262,6 +2294,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.alive = (unsigned long long*)(p + l.off_alive);
     s.rho = (unsigned long long*)(p + l.off_rho);
     s.rhs = (unsigned long long*)(p + l.off_rhs);
+    s.unc = (unsigned long long*)(p + l.off_unc);
     s.tsel = (int32_t*)(p + l.off_tsel);
     s.tref = (int32_t*)(p + l.off_tref);
     s.hot = (int32_t*)(p + l.off_hot);
