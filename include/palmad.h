@@ -259,6 +259,48 @@ int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m
                           void* stream);
 
 /*
+ * The discord heatmap (Sec. 5, Eq. (11)): palmad_discords() that also keeps,
+ * for every length m, all the range discords of the successful range search
+ * (every subsequence whose nearest non-self match is at distance >= r_m) with
+ * their exact nearest-neighbour distances.  heat(m, i) = nnDist^2 / (2m) =
+ * 1 - rho (the distance in squared z-normalised units over 2m, in [0, 2]) for
+ * the range discords of length m, 0 for every other i.  Every range search
+ * refines both sides exactly, so this runs slower than palmad_discords().
+ *
+ *   T ... count, stats, stream  as palmad_discords() (same workspace size).
+ *   heat       device, float64[L * ld]: row m - minL, columns i < ld; columns
+ *              >= n - m + 1 are 0.
+ *   ld         row stride of heat, >= n - minL + 1.
+ *   range      device, float64[L]: r_m of the successful range search of
+ *              each length (<= 0 means every subsequence).
+ */
+int palmad_discord_heatmap(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL,
+                           int32_t maxL, int32_t k, const palmad_options* opts, void* workspace,
+                           size_t ws_bytes, int64_t* idx, int32_t* len, double* nn_dist,
+                           int64_t* nn_idx, int32_t* count, double* heat, int64_t ld,
+                           double* range, palmad_stats* stats, void* stream);
+
+/*
+ * Discord interest (Sec. 5, Eq. (12)): for every column i of a heatmap the
+ * largest value over the lengths (ties: the shorter length), and the k
+ * columns with the largest such values (ties: the smaller index; columns
+ * whose value is 0 hold no discord).
+ *
+ *   heat       device, float64[L * ld] as written by palmad_discord_heatmap().
+ *   L, ld      rows (lengths) and row stride; ncols <= ld columns are read.
+ *   minL       length of row 0.
+ *   k          1 <= k <= ncols.
+ *   col_score  device, float64[ncols]: max over m of heat(m, i).
+ *   col_len    device, int32[ncols]: the length m attaining it.
+ *   top_idx    device, int64[k]; top_len device, int32[k]; top_score device,
+ *              float64[k]: the k most interesting columns, best first.
+ */
+int palmad_heatmap_interest(palmad_ctx* ctx, const double* heat, int32_t L, int64_t ld,
+                            int64_t ncols, int32_t minL, int32_t k, double* col_score,
+                            int32_t* col_len, int64_t* top_idx, int32_t* top_len,
+                            double* top_score, void* stream);
+
+/*
  * Bytes of device workspace palmad_discords_backward() needs for K reported
  * rows of lengths <= maxm in a series of length n.  Pure host computation;
  * PALMAD_EINVAL unless 3 <= maxm, n >= 3*maxm - 1 and K >= 0.

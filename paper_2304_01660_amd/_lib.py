@@ -115,6 +115,12 @@ SIGNATURES = {
                                              ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
                                              _vp, ctypes.POINTER(_i64), ctypes.POINTER(Stats),
                                              _vp]),
+    "palmad_discord_heatmap": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32,
+                                              ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
+                                              _vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                              ctypes.POINTER(Stats), _vp]),
+    "palmad_heatmap_interest": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i64, _i32, _i32, _vp, _vp,
+                                               _vp, _vp, _vp, _vp]),
     "palmad_window_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                            _vp, _vp]),
     "palmad_backward_workspace_size": (ctypes.c_int, [_i64, _i64, _i32,

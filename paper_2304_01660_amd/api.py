@@ -100,6 +100,78 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
     return out
 
 
+def discord_heatmap(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
+                    guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0,
+                    return_stats: bool = False, rows_near: int = 0, rows_far: int = 0,
+                    rows_refine: int = 0, far_grid: int = 0, graphs: bool = True):
+    """Top-k discords of every length plus the discord heatmap (Eq. (11)).
+
+    Returns the dict of ``discords`` plus ``heat`` float64[L, n - minL + 1]
+    (row m - minL: nnDist^2 / (2m) = 1 - rho of every range discord of length
+    m, 0 elsewhere) and ``range`` float64[L] (r of each length's successful
+    range search).
+    """
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    L = maxL - minL + 1
+    ld = n - minL + 1
+    o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, False, rows_near, rows_far,
+                          rows_refine, far_grid, graphs)
+    nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
+                            near_cols=near_cols, chunk_cols=chunk_cols)
+    ws = _workspace(nbytes, dev)
+    out = {
+        "idx": torch.empty(L * k, dtype=torch.int64, device=dev),
+        "len": torch.empty(L * k, dtype=torch.int32, device=dev),
+        "nn_dist": torch.empty(L * k, dtype=torch.float64, device=dev),
+        "nn_idx": torch.empty(L * k, dtype=torch.int64, device=dev),
+        "count": torch.empty(L, dtype=torch.int32, device=dev),
+        "heat": torch.empty((L, ld), dtype=torch.float64, device=dev),
+        "range": torch.empty(L, dtype=torch.float64, device=dev),
+    }
+    st = _lib.Stats()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_discord_heatmap(
+        ctx, ctypes.c_void_p(T.data_ptr()), n, minL, maxL, k, ctypes.byref(o),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out["idx"].data_ptr()),
+        ctypes.c_void_p(out["len"].data_ptr()), ctypes.c_void_p(out["nn_dist"].data_ptr()),
+        ctypes.c_void_p(out["nn_idx"].data_ptr()), ctypes.c_void_p(out["count"].data_ptr()),
+        ctypes.c_void_p(out["heat"].data_ptr()), ld, ctypes.c_void_p(out["range"].data_ptr()),
+        ctypes.byref(st), _stream(dev))
+    _lib.check(rc, ctx)
+    if return_stats:
+        out["stats"] = st.as_dict()
+    return out
+
+
+def heatmap_interest(heat: torch.Tensor, minL: int, k: int):
+    """Discord interest (Eq. (12)) of a heatmap [L, ncols] from discord_heatmap.
+
+    Returns (col_score float64[ncols], col_len int32[ncols], top_idx int64[k],
+    top_len int32[k], top_score float64[k]) as device tensors: per column the
+    largest value over the lengths and its length, and the k best columns.
+    """
+    if heat.dim() != 2 or heat.dtype != torch.float64 or not heat.is_cuda:
+        raise ValueError("heat must be a 2-D float64 CUDA tensor")
+    heat = heat.contiguous()
+    dev = heat.device
+    L, ncols = heat.shape
+    col_score = torch.empty(ncols, dtype=torch.float64, device=dev)
+    col_len = torch.empty(ncols, dtype=torch.int32, device=dev)
+    top_idx = torch.empty(k, dtype=torch.int64, device=dev)
+    top_len = torch.empty(k, dtype=torch.int32, device=dev)
+    top_score = torch.empty(k, dtype=torch.float64, device=dev)
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_heatmap_interest(
+        ctx, ctypes.c_void_p(heat.data_ptr()), L, ncols, ncols, minL, k,
+        ctypes.c_void_p(col_score.data_ptr()), ctypes.c_void_p(col_len.data_ptr()),
+        ctypes.c_void_p(top_idx.data_ptr()), ctypes.c_void_p(top_len.data_ptr()),
+        ctypes.c_void_p(top_score.data_ptr()), _stream(dev))
+    _lib.check(rc, ctx)
+    return col_score, col_len, top_idx, top_len, top_score
+
+
 def batched_workspace_size(lengths, minL, maxL, k: int, **opts) -> int:
     """Workspace bytes of discords_batched for series of the given lengths."""
     B = len(lengths)

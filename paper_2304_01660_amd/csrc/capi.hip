@@ -230,6 +230,9 @@ struct Outputs {
     double* nn;
     int64_t* nnidx;
     int32_t* count;
+    double* heat = nullptr;   // discord heatmap (optional)
+    double* rlen = nullptr;
+    int64_t heat_ld = 0;
 };
 
 // Write the descriptors and prefix tables into the workspace (one upload).
@@ -247,6 +250,9 @@ int upload(palmad_ctx* ctx, const Plan& p, void* ws, const double* const* Tin, c
             s.nn = outs[b].nn;
             s.nnidx = outs[b].nnidx;
             s.count = outs[b].count;
+            s.heat = outs[b].heat;
+            s.rlen = outs[b].rlen;
+            s.heat_ld = outs[b].heat_ld;
         }
         d[b] = s;
     }
@@ -637,6 +643,53 @@ int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, i
     if (rc) return rc;
     const Outputs out = {idx, len, nn_dist, nn_idx, count};
     return search(ctx, p, o, workspace, &T, &out, stats, stream);
+}
+
+int palmad_discord_heatmap(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL,
+                           int32_t maxL, int32_t k, const palmad_options* opts, void* workspace,
+                           size_t ws_bytes, int64_t* idx, int32_t* len, double* nn_dist,
+                           int64_t* nn_idx, int32_t* count, double* heat, int64_t ld,
+                           double* range, palmad_stats* stats, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!T || !idx || !len || !nn_dist || !nn_idx || !count || !heat || !range)
+        return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    int rc = validate(ctx, n, minL, maxL, k);
+    if (rc) return rc;
+    if (ld < n - minL + 1)
+        return fail(ctx, PALMAD_EINVAL, "ld (%lld) < n - minL + 1 (%lld)", (long long)ld,
+                    (long long)(n - minL + 1));
+    Opts o;
+    rc = read_opts(ctx, opts, &o);
+    if (rc) return rc;
+    Plan p;
+    make_plan(1, &n, &minL, &maxL, k, cfg_of(o, nullptr), &p);
+    rc = check_ws(ctx, workspace, ws_bytes, p.total);
+    if (rc) return rc;
+    Outputs out = {idx, len, nn_dist, nn_idx, count};
+    out.heat = heat;
+    out.rlen = range;
+    out.heat_ld = ld;
+    return search(ctx, p, o, workspace, &T, &out, stats, stream);
+}
+
+int palmad_heatmap_interest(palmad_ctx* ctx, const double* heat, int32_t L, int64_t ld,
+                            int64_t ncols, int32_t minL, int32_t k, double* col_score,
+                            int32_t* col_len, int64_t* top_idx, int32_t* top_len,
+                            double* top_score, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!heat || !col_score || !col_len || !top_idx || !top_len || !top_score)
+        return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    if (L < 1 || ncols < 1 || ld < ncols)
+        return fail(ctx, PALMAD_EINVAL, "need L >= 1, ncols >= 1 and ld >= ncols");
+    if (k < 1 || (int64_t)k > ncols) return fail(ctx, PALMAD_EINVAL, "k must be in [1, ncols]");
+    if (minL < 1) return fail(ctx, PALMAD_EINVAL, "minL must be >= 1");
+    int rc = enter(ctx, stream);
+    if (rc) return rc;
+    HIP_TRY(launch_interest(heat, L, ld, ncols, minL, k, col_score, col_len, top_idx, top_len,
+                            top_score, ctx->work));
+    return leave(ctx, stream);
 }
 
 int palmad_batched_workspace_size(int32_t B, const int64_t* offsets, const int32_t* minL,

@@ -123,6 +123,11 @@ struct SeriesDev {
     double* nn;
     int64_t* nnidx;
     int32_t* count;
+    // discord heatmap (NULL unless requested): heat[(m - minL) * heat_ld + i],
+    // the final range r of every length in rlen[m - minL]
+    double* heat;
+    double* rlen;
+    int64_t heat_ld;
 };
 
 // Per-series layout (host side; offsets relative to the series' base).
@@ -200,6 +205,11 @@ hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_
 hipError_t launch_nonfinite(const Batch& bt, int32_t* out, hipStream_t st);
 hipError_t launch_set_len(const Batch& bt, int32_t m, hipStream_t st);
 hipError_t launch_stats_out(const Batch& bt, int64_t N, double* mu, double* sigma, hipStream_t st);
+// Interest of every heatmap column (largest value over the lengths, and that
+// length) and the k most interesting columns.
+hipError_t launch_interest(const double* heat, int32_t L, int64_t ld, int64_t ncols, int32_t minL,
+                           int32_t k, double* col_score, int32_t* col_len, int64_t* top_idx,
+                           int32_t* top_len, double* top_score, hipStream_t st);
 hipError_t launch_adjoint(const double* Tpad, int64_t n, int64_t K, int32_t maxm,
                           const int64_t* idx, const int32_t* len, const double* gin,
                           const Ctrl* ctrl, double* part, int64_t nblk, double* grad,

@@ -1377,8 +1377,9 @@ __global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, in
         // recorded one, so the right side needs the exact sweep only when
         // some live row's recorded maximum is above thr64 - g (or when there
         // was no selection sweep, or the round is an exact repeat, or a bare
-        // range search, which reports every survivor's exact maximum).
-        both = !c->prune || c->exact_ref || c->mode == 3;
+        // range search or a heatmap, which report every survivor's exact
+        // maximum).
+        both = !c->prune || c->exact_ref || c->mode == 3 || s.heat != nullptr;
         if (!both) {
             unsigned long long u = 0ull;
             for (int w = 0; w < words; ++w) u |= s.alive[t * words + w] & s.unc[t * words + w];
@@ -1508,7 +1509,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
     // ranking key of a live row: its refined maximum, or, where refinement
     // swept only the left side, the larger of that and the selection sweep's
     // (within the guard of exact); an exact repeat ranks by exact values
-    const bool exact = c->exact_ref || !c->prune || c->mode == 3;
+    const bool exact = c->exact_ref || !c->prune || c->mode == 3 || s.heat != nullptr;
     auto key_of = [&](long long i) -> unsigned long long {
         return exact ? rho[i] : (rho[i] > rhs[i] ? rho[i] : rhs[i]);
     };
@@ -1913,6 +1914,7 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
             }
         }
     }
+    if (s.heat) __threadfence();  // the direct round's bitmap and rho updates, read below
     __syncthreads();
     if (tid == 0) {
         unsigned int nv = 0;
@@ -1943,6 +1945,23 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
         }
     }
     __syncthreads();
+    if (ok && s.heat) {
+        // the discord heatmap row of this length (Eq. (11)): every range
+        // discord (the alive bits) with its exact nearest-neighbour
+        // correlation, as ED^2 / (2m) = 1 - rho; 0 elsewhere
+        const int64_t N = s.n - m + 1;
+        double* hrow = s.heat + (int64_t)li * s.heat_ld;
+        for (int64_t i = tid; i < s.heat_ld; i += END_BLOCK) {
+            double v = 0.0;
+            if (i < N && ((load_word(&s.alive[i >> 6]) >> (i & 63)) & 1ull)) {
+                const double rh =
+                    dbl_of(__hip_atomic_load(&s.rho[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                v = fmin(2.0, fmax(0.0, 1.0 - rh));
+            }
+            hrow[i] = v;
+        }
+        if (tid == 0) s.rlen[li] = c->r;
+    }
     if (tid == 0) {
         c->rounds += 1;
         c->nsurv = ns;
@@ -2219,6 +2238,99 @@ hipError_t launch_stats_out(const Batch& bt, int64_t N, double* mu, double* sigm
 // ---------------------------------------------------------------------------
 // per-series workspace layout and work geometry
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// discord interest (Eq. (12)): per heatmap column the largest value over the
+// lengths (ties: the shorter length), then the k columns with the largest
+// values (ties: the smaller index)
+// ---------------------------------------------------------------------------
+__global__ void k_interest_cols(const double* __restrict__ heat, int32_t L, int64_t ld,
+                                int64_t ncols, int32_t minL, double* score, int32_t* blen)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncols) return;
+    double best = heat[i];
+    int32_t bm = 0;
+    for (int32_t l = 1; l < L; ++l) {
+        const double v = heat[(int64_t)l * ld + i];
+        if (v > best) {
+            best = v;
+            bm = l;
+        }
+    }
+    score[i] = best;
+    blen[i] = minL + bm;
+}
+
+constexpr int INTEREST_BLOCK = 1024;
+__global__ __launch_bounds__(INTEREST_BLOCK) void k_interest_top(const double* __restrict__ score,
+                                                                const int32_t* __restrict__ blen,
+                                                                int64_t ncols, int32_t k,
+                                                                int64_t* top_idx, int32_t* top_len,
+                                                                double* top_score)
+{
+    __shared__ double bv_s[INTEREST_BLOCK / 64];
+    __shared__ long long bi_s[INTEREST_BLOCK / 64];
+    __shared__ double lastv_s;
+    __shared__ long long lasti_s;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // order: larger score first, then smaller index; round r takes the best
+    // column strictly after round r - 1's in that order
+    for (int r = 0; r < k; ++r) {
+        const double lv = r ? lastv_s : 0.0;
+        const long long li = r ? lasti_s : -1;
+        double bv = -1.0;
+        long long bi = -1;
+        for (int64_t i = tid; i < ncols; i += INTEREST_BLOCK) {
+            const double v = score[i];
+            const bool after = r == 0 || v < lv || (v == lv && i > li);
+            if (after && (v > bv || (v == bv && (bi < 0 || i < bi)))) {
+                bv = v;
+                bi = i;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double v = __shfl_xor(bv, o);
+            const long long j = __shfl_xor(bi, o);
+            if (j >= 0 && (bi < 0 || v > bv || (v == bv && j < bi))) {
+                bv = v;
+                bi = j;
+            }
+        }
+        if (lane == 0) {
+            bv_s[w] = bv;
+            bi_s[w] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = bv_s[0];
+            long long j = bi_s[0];
+            for (int q = 1; q < INTEREST_BLOCK / 64; ++q)
+                if (bi_s[q] >= 0 && (j < 0 || bv_s[q] > v || (bv_s[q] == v && bi_s[q] < j))) {
+                    v = bv_s[q];
+                    j = bi_s[q];
+                }
+            top_idx[r] = j;
+            top_len[r] = j >= 0 ? blen[j] : 0;
+            top_score[r] = j >= 0 ? v : 0.0;
+            lastv_s = v;
+            lasti_s = j;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_interest(const double* heat, int32_t L, int64_t ld, int64_t ncols, int32_t minL,
+                           int32_t k, double* col_score, int32_t* col_len, int64_t* top_idx,
+                           int32_t* top_len, double* top_score, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_interest_cols, dim3((unsigned int)((ncols + 255) / 256)), dim3(256), 0, st,
+                       heat, L, ld, ncols, minL, col_score, col_len);
+    hipLaunchKernelGGL(k_interest_top, dim3(1), dim3(INTEREST_BLOCK), 0, st, col_score, col_len,
+                       ncols, k, top_idx, top_len, top_score);
+    return hipGetLastError();
+}
+
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
