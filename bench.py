@@ -132,6 +132,51 @@ def batched_vs_plain(api, synth, tuning, torch, dev, reps: int, retune: bool):
     }
 
 
+def heatmap_leg(api, torch, dev, w, T, tuned, ms_plain, plain_out, reps: int = 3):
+    """The discord heatmap search (Eq. (11)) on the same workload, and the
+    interest kernels (Eq. (12)) on its heatmap, timed on the GPU."""
+    opts = dict(tuned or {})
+    L = w.maxL - w.minL + 1
+    api.discord_heatmap(T, w.minL, w.maxL, w.k, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hm = api.discord_heatmap(T, w.minL, w.maxL, w.k, **opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    same = bool(torch.equal(hm["idx"], plain_out["idx"]))
+    heat = hm["heat"]
+    ncols = heat.shape[1]
+    api.heatmap_interest(heat, w.minL, w.k)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    ir = 10
+    for _ in range(ir):
+        api.heatmap_interest(heat, w.minL, w.k)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ims = e0.elapsed_time(e1) / ir
+    nbytes = L * ncols * 8 + ncols * 12 + w.k * 20
+    return {
+        "workload": w.name,
+        "ms_per_search": ms,
+        "lengths_per_s": L / (ms * 1e-3),
+        "slowdown_vs_top_k_only": ms / ms_plain,
+        "top_k_identical_to_plain_search": same,
+        "range_discords_total": int(hm["count"].sum().item()),
+        "interest": {
+            "ms": ims,
+            "columns": ncols,
+            "algorithmic_bytes": nbytes,
+            "achieved_GBps": nbytes / (ims * 1e-3) / 1e9,
+            "peak_GBps": 8000.0,
+            "frac": nbytes / (ims * 1e-3) / 8e12,
+            "bound": "hbm",
+        },
+    }
+
+
 def measured_traffic(kernel: str, workload: str, options: dict):
     """HBM bytes per launch of `kernel` from the stored hardware-counter
     summary under profiles/, if it was taken on this exact kernel source,
@@ -178,6 +223,8 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner now instead of using the stored tile options")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--no-heatmap", action="store_true",
+                    help="skip the discord heatmap / interest leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding "
@@ -282,6 +329,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = batched_vs_plain(api, synth, tuning, torch, dev, args.batch_reps, args.retune)
+    heat = None
+    if not args.no_heatmap:
+        heat = heatmap_leg(api, torch, dev, w, T, tuned, ms_per_step, out)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_lengths)
@@ -313,6 +363,7 @@ def main():
         "parity_vs_oracle": parity,
         "roofline": roofline,
         "batched": batched,
+        "heatmap": heat,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
