@@ -2248,14 +2248,19 @@ __global__ void k_interest_cols(const double* __restrict__ heat, int32_t L, int6
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncols) return;
-    double best = heat[i];
+    // eight rows' loads are issued before they are compared
+    double best = -1.0;
     int32_t bm = 0;
-    for (int32_t l = 1; l < L; ++l) {
-        const double v = heat[(int64_t)l * ld + i];
-        if (v > best) {
-            best = v;
-            bm = l;
-        }
+    for (int32_t l0 = 0; l0 < L; l0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = l0 + u < L ? heat[(int64_t)(l0 + u) * ld + i] : -1.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (v[u] > best) {
+                best = v[u];
+                bm = l0 + u;
+            }
     }
     score[i] = best;
     blen[i] = minL + bm;
@@ -2280,12 +2285,22 @@ __global__ __launch_bounds__(INTEREST_BLOCK) void k_interest_top(const double* _
         const long long li = r ? lasti_s : -1;
         double bv = -1.0;
         long long bi = -1;
-        for (int64_t i = tid; i < ncols; i += INTEREST_BLOCK) {
-            const double v = score[i];
-            const bool after = r == 0 || v < lv || (v == lv && i > li);
-            if (after && (v > bv || (v == bv && (bi < 0 || i < bi)))) {
-                bv = v;
-                bi = i;
+        for (int64_t i0 = tid; i0 < ncols; i0 += 4 * INTEREST_BLOCK) {
+            double vs[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = i0 + (int64_t)u * INTEREST_BLOCK;
+                vs[u] = i < ncols ? score[i] : -1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = i0 + (int64_t)u * INTEREST_BLOCK;
+                const double v = vs[u];
+                const bool after = r == 0 || v < lv || (v == lv && i > li);
+                if (i < ncols && after && (v > bv || (v == bv && (bi < 0 || i < bi)))) {
+                    bv = v;
+                    bi = i;
+                }
             }
         }
 #pragma unroll
