@@ -545,7 +545,7 @@ int time_probe(palmad_ctx* ctx, const Probe& pr, int32_t k, const Opts& o, void*
 
 extern "C" {
 
-const char* palmad_version(void) { return "palmad-mi355x 0.2 (gfx950)"; }
+const char* palmad_version(void) { return "palmad-mi355x 0.3 (gfx950)"; }
 
 const char* palmad_last_error(const palmad_ctx* ctx)
 {
