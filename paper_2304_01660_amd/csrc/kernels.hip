@@ -2285,15 +2285,15 @@ __global__ __launch_bounds__(INTEREST_BLOCK) void k_interest_top(const double* _
         const long long li = r ? lasti_s : -1;
         double bv = -1.0;
         long long bi = -1;
-        for (int64_t i0 = tid; i0 < ncols; i0 += 4 * INTEREST_BLOCK) {
-            double vs[4];
+        for (int64_t i0 = tid; i0 < ncols; i0 += 16 * INTEREST_BLOCK) {
+            double vs[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int64_t i = i0 + (int64_t)u * INTEREST_BLOCK;
                 vs[u] = i < ncols ? score[i] : -1.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int64_t i = i0 + (int64_t)u * INTEREST_BLOCK;
                 const double v = vs[u];
                 const bool after = r == 0 || v < lv || (v == lv && i > li);
