@@ -177,6 +177,37 @@ def heatmap_leg(api, torch, dev, w, T, tuned, ms_plain, plain_out, reps: int = 3
     }
 
 
+def dense_leg(api, torch, w, T, tuned, ms_plain, reps: int = 3):
+    """The dense exact matrix profile at one length (a range search with
+    r = 0: no pruning, every pair swept in FP64 on both sides), against the
+    pruned search's time per length: whether pruning pays on this GPU."""
+    m = (w.minL + w.maxL) // 2
+    opts = dict(tuned or {})
+    api.range_discords(T, m, 0.0, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        api.range_discords(T, m, 0.0, **opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    _, _, cnt, st = api.range_discords(T, m, 0.0, return_stats=True, time_kernels=True, **opts)
+    ev = st["kernel_evals"][2]
+    kms = st["kernel_ms"][2]
+    lanes = ev * OPS_PER_EVAL / (kms * 1e-3) / 1e12 if kms > 0 else None
+    L = w.maxL - w.minL + 1
+    return {
+        "m": m,
+        "ms": ms,
+        "subsequences": cnt,
+        "pair_evaluations": ev,
+        "refine_kernel_ms": kms,
+        "refine_Tlane_ops_per_s": lanes,
+        "refine_frac_of_valu_peak": lanes / VALU_PEAK_TOPS if lanes else None,
+        "pruned_search_ms_per_length": ms_plain / L,
+        "pruning_speedup": ms / (ms_plain / L),
+    }
+
+
 def measured_traffic(kernel: str, workload: str, options: dict):
     """HBM bytes per launch of `kernel` from the stored hardware-counter
     summary under profiles/, if it was taken on this exact kernel source,
@@ -225,6 +256,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--no-heatmap", action="store_true",
                     help="skip the discord heatmap / interest leg")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense matrix-profile leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding "
@@ -332,6 +365,9 @@ def main():
     heat = None
     if not args.no_heatmap:
         heat = heatmap_leg(api, torch, dev, w, T, tuned, ms_per_step, out)
+    dense = None
+    if not args.no_dense:
+        dense = dense_leg(api, torch, w, T, tuned, ms_per_step)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_lengths)
@@ -364,6 +400,7 @@ def main():
         "roofline": roofline,
         "batched": batched,
         "heatmap": heat,
+        "dense_matrix_profile": dense,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
