@@ -260,8 +260,9 @@ def main():
                     help="skip the dense matrix-profile leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding "
-              "is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              "multi-GPU path (sharding across GPUs is described, not implemented)",
+              file=sys.stderr)
         return 2
 
     import torch

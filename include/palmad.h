@@ -51,7 +51,7 @@ typedef enum {
     PALMAD_EWORKSPACE = -3,   /* workspace smaller than palmad_workspace_size() */
     PALMAD_EDEVICE = -4,      /* a HIP call failed */
     PALMAD_ENOMEM = -5,       /* host allocation failed */
-    PALMAD_EUNSUPPORTED = -6  /* valid request outside what this build supports */
+    PALMAD_EUNSUPPORTED = -6  /* valid request outside what this library supports */
 } palmad_status;
 
 /* Options; a zero-initialised struct selects the defaults. */
