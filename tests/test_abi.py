@@ -82,6 +82,10 @@ def test_null_pointer_arguments_are_rejected():
     assert L.palmad_create(None, 0) == -1
     assert L.palmad_discords(None, None, 1000, 10, 20, 1, None, None, 0, None, None, None,
                              None, None, None, None) == -1
+    assert L.palmad_discord_heatmap(None, None, 1000, 10, 20, 1, None, None, 0, None, None,
+                                    None, None, None, None, 991, None, None, None) == -1
+    assert L.palmad_heatmap_interest(None, None, 11, 991, 991, 10, 1, None, None, None, None,
+                                     None, None) == -1
     L.palmad_destroy(None)
 
 
