@@ -30,15 +30,40 @@
  *     that spread is zero, r is lowered by 1% instead.
  *   - Ties: larger nnDist first, then smaller index; a nearest neighbour
  *     tie keeps the smaller neighbour index.
+ *
+ * Built plainly this file is serial.  Built with -fopenmp (the second
+ * library the Python wrapper offers, for the largest workloads), the inner
+ * loop over the current candidates of each scanned subsequence in both DRAG
+ * phases is split over threads once the candidate list is long.  Every
+ * decision in that loop depends only on the pair (scanned subsequence,
+ * candidate) and on the candidate's own running nearest-neighbour state, so
+ * the scan order of Alg. 2 and every result (indices, distances, neighbour
+ * indices, evaluation counts) are the same as the serial build's.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL -1
 #define OR_ENOMEM -5
+
+/* Threads the OpenMP build uses after this call (want > 0 sets it); the
+   serial build always reports 1. */
+int oracle_threads(int want)
+{
+#ifdef _OPENMP
+    if (want > 0) omp_set_num_threads(want);
+    return omp_get_max_threads();
+#else
+    (void)want;
+    return 1;
+#endif
+}
 
 /* Flat-window threshold factor (see header). */
 static const double FLAT_REL = 1e-12;
@@ -86,7 +111,6 @@ typedef struct {
     double* mu;
     double* sigma;
     unsigned char* flat;
-    uint64_t evals;     /* distance evaluations started */
 } series_m;
 
 static int series_m_init(series_m* s, const double* T, int64_t n, int32_t m, double flat_eps)
@@ -95,7 +119,6 @@ static int series_m_init(series_m* s, const double* T, int64_t n, int32_t m, dou
     s->n = n;
     s->m = m;
     s->N = n - m + 1;
-    s->evals = 0;
     s->mu = (double*)malloc(sizeof(double) * (size_t)s->N);
     s->sigma = (double*)malloc(sizeof(double) * (size_t)s->N);
     s->flat = (unsigned char*)malloc((size_t)s->N);
@@ -123,9 +146,8 @@ static void series_m_free(series_m* s)
  * `bound2` (the EarlyAbandonED procedure of Sec. 2.2); the partial sum is
  * returned then, which is >= bound2.
  */
-static double zdist2(series_m* s, int64_t i, int64_t j, double bound2)
+static double zdist2(const series_m* s, int64_t i, int64_t j, double bound2)
 {
-    s->evals++;
     if (s->flat[i] || s->flat[j]) {
         if (s->flat[i] && s->flat[j]) return 0.0;
         return 2.0 * (double)s->m;
@@ -162,55 +184,151 @@ static int64_t iabs64(int64_t a) { return a < 0 ? -a : a; }
  * range discords) in increasing index order; the count is returned via
  * *out_count.  Buffers must hold N = n - m + 1 entries.
  */
-static int drag_core(series_m* s, double r, int64_t* out_idx, double* out_nn, int64_t* out_nnidx,
-                     int64_t* out_count)
+/* Candidate lists at least this long have their inner loop split over
+   threads in the OpenMP build; shorter ones stay serial (thread start-up
+   would cost more than the loop). */
+#define PAR_MIN_CANDIDATES 256
+
+/*
+ * Phase 1 inner step for the candidates cand[a0 .. a1): hit[a] = 1 when
+ * candidate cand[a] is a non-self match of subsequence sidx closer than r.
+ * Returns the number of distance evaluations made.
+ */
+static uint64_t phase1_hits(const series_m* s, int64_t sidx, const int64_t* cand, int64_t a0,
+                            int64_t a1, double r2, unsigned char* hit)
+{
+    uint64_t ev = 0;
+    for (int64_t a = a0; a < a1; ++a) {
+        int64_t c = cand[a];
+        hit[a] = 0;
+        if (iabs64(sidx - c) >= s->m) {
+            ++ev;
+            if (zdist2(s, sidx, c, r2) < r2) hit[a] = 1;
+        }
+    }
+    return ev;
+}
+
+/*
+ * Phase 2 inner step for the candidates cand[a0 .. a1) against subsequence
+ * sidx: a non-self match closer than r marks the candidate dead (hit = 1);
+ * otherwise a closer match updates the candidate's nearest neighbour (strict
+ * <, so the first, i.e. smallest, index wins ties).  Returns the number of
+ * distance evaluations made.
+ */
+static uint64_t phase2_step(const series_m* s, int64_t sidx, const int64_t* cand, int64_t a0,
+                            int64_t a1, int prune, double r2, double* nn2, int64_t* nnj,
+                            unsigned char* hit)
+{
+    uint64_t ev = 0;
+    for (int64_t a = a0; a < a1; ++a) {
+        int64_t c = cand[a];
+        hit[a] = 0;
+        if (iabs64(sidx - c) >= s->m) {
+            ++ev;
+            double d2 = zdist2(s, sidx, c, nn2[c]);
+            if (prune && d2 < r2) {
+                hit[a] = 1;
+            } else if (d2 < nn2[c]) {
+                nn2[c] = d2;
+                nnj[c] = sidx;
+            }
+        }
+    }
+    return ev;
+}
+
+#ifdef _OPENMP
+static uint64_t phase1_hits_par(const series_m* s, int64_t sidx, const int64_t* cand, int64_t nc,
+                                double r2, unsigned char* hit)
+{
+    uint64_t ev = 0;
+    int64_t chunk = 64;
+#pragma omp parallel for schedule(dynamic) reduction(+ : ev)
+    for (int64_t a0 = 0; a0 < nc; a0 += chunk) {
+        int64_t a1 = a0 + chunk < nc ? a0 + chunk : nc;
+        ev += phase1_hits(s, sidx, cand, a0, a1, r2, hit);
+    }
+    return ev;
+}
+
+static uint64_t phase2_step_par(const series_m* s, int64_t sidx, const int64_t* cand, int64_t nc,
+                                int prune, double r2, double* nn2, int64_t* nnj,
+                                unsigned char* hit)
+{
+    uint64_t ev = 0;
+    int64_t chunk = 64;
+#pragma omp parallel for schedule(dynamic) reduction(+ : ev)
+    for (int64_t a0 = 0; a0 < nc; a0 += chunk) {
+        int64_t a1 = a0 + chunk < nc ? a0 + chunk : nc;
+        ev += phase2_step(s, sidx, cand, a0, a1, prune, r2, nn2, nnj, hit);
+    }
+    return ev;
+}
+#endif
+
+/*
+ * DRAG (Alg. 2) at length m with range r.
+ *
+ * Phase 1 (candidate selection): scan the subsequences in order; every
+ * candidate that is a non-self match of the scanned subsequence and closer
+ * than r is dropped, and the scanned subsequence becomes a candidate only if
+ * it was closer than r to none of them.
+ *
+ * Phase 2 (refinement): scan all subsequences again; a candidate with a
+ * non-self match closer than r is dropped, otherwise its nearest-neighbour
+ * distance is the minimum over all of its non-self matches, found with
+ * early abandoning at the current best.
+ *
+ * On return out_idx/out_nn/out_nnidx hold the surviving candidates (the
+ * range discords) in increasing index order; the count is returned via
+ * *out_count and the number of distance evaluations is added to *evals.
+ * Buffers must hold N = n - m + 1 entries.
+ */
+static int drag_core(const series_m* s, double r, int64_t* out_idx, double* out_nn,
+                     int64_t* out_nnidx, int64_t* out_count, uint64_t* evals)
 {
     const int64_t N = s->N;
-    const int32_t m = s->m;
     const int prune = r > 0.0;
     const double r2 = prune ? r * r : 0.0;
+    uint64_t ev = 0;
 
-    /* ---- phase 1 ---- */
     int64_t* cand = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
-    unsigned char* alive = (unsigned char*)calloc((size_t)N, 1);
-    if (!cand || !alive) {
+    unsigned char* hit = (unsigned char*)malloc((size_t)N);
+    double* nn2 = (double*)malloc(sizeof(double) * (size_t)N);
+    int64_t* nnj = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    if (!cand || !hit || !nn2 || !nnj) {
         free(cand);
-        free(alive);
+        free(hit);
+        free(nn2);
+        free(nnj);
         return OR_ENOMEM;
     }
+
+    /* ---- phase 1 ---- */
     int64_t nc = 0;
     cand[nc++] = 0;
     for (int64_t sidx = 1; sidx < N; ++sidx) {
         int is_cand = 1;
         if (prune) {
+#ifdef _OPENMP
+            if (nc >= PAR_MIN_CANDIDATES)
+                ev += phase1_hits_par(s, sidx, cand, nc, r2, hit);
+            else
+#endif
+                ev += phase1_hits(s, sidx, cand, 0, nc, r2, hit);
+            /* drop every hit candidate, keeping the list in index order */
             int64_t w = 0;
             for (int64_t a = 0; a < nc; ++a) {
-                int64_t c = cand[a];
-                int keep = 1;
-                if (iabs64(sidx - c) >= m) {
-                    if (zdist2(s, sidx, c, r2) < r2) {
-                        keep = 0;
-                        is_cand = 0;
-                    }
-                }
-                if (keep) cand[w++] = c;
+                if (hit[a]) is_cand = 0;
+                else cand[w++] = cand[a];
             }
             nc = w;
         }
         if (is_cand) cand[nc++] = sidx;
     }
-    for (int64_t a = 0; a < nc; ++a) alive[cand[a]] = 1;
 
     /* ---- phase 2 ---- */
-    double* nn2 = (double*)malloc(sizeof(double) * (size_t)N);
-    int64_t* nnj = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
-    if (!nn2 || !nnj) {
-        free(cand);
-        free(alive);
-        free(nn2);
-        free(nnj);
-        return OR_ENOMEM;
-    }
     for (int64_t a = 0; a < nc; ++a) {
         nn2[cand[a]] = INFINITY;
         nnj[cand[a]] = -1;
@@ -219,35 +337,27 @@ static int drag_core(series_m* s, double r, int64_t* out_idx, double* out_nn, in
        order and removal keeps relative order), so dead entries can be
        compacted out as the scan proceeds. */
     for (int64_t sidx = 0; sidx < N; ++sidx) {
+#ifdef _OPENMP
+        if (nc >= PAR_MIN_CANDIDATES)
+            ev += phase2_step_par(s, sidx, cand, nc, prune, r2, nn2, nnj, hit);
+        else
+#endif
+            ev += phase2_step(s, sidx, cand, 0, nc, prune, r2, nn2, nnj, hit);
         int64_t w = 0;
-        for (int64_t a = 0; a < nc; ++a) {
-            int64_t c = cand[a];
-            if (iabs64(sidx - c) >= m) {
-                double d2 = zdist2(s, sidx, c, nn2[c]);
-                if (prune && d2 < r2) {
-                    alive[c] = 0;
-                    continue;          /* drop c from the candidate list */
-                }
-                if (d2 < nn2[c]) {
-                    nn2[c] = d2;
-                    nnj[c] = sidx;
-                }
-            }
-            cand[w++] = c;
-        }
+        for (int64_t a = 0; a < nc; ++a)
+            if (!hit[a]) cand[w++] = cand[a];
         nc = w;
     }
-    int64_t cnt = 0;
     for (int64_t a = 0; a < nc; ++a) {
         int64_t c = cand[a];
-        out_idx[cnt] = c;
-        out_nn[cnt] = sqrt(nn2[c]);
-        out_nnidx[cnt] = nnj[c];
-        ++cnt;
+        out_idx[a] = c;
+        out_nn[a] = sqrt(nn2[c]);
+        out_nnidx[a] = nnj[c];
     }
-    *out_count = cnt;
+    *out_count = nc;
+    *evals += ev;
     free(cand);
-    free(alive);
+    free(hit);
     free(nn2);
     free(nnj);
     return OR_OK;
@@ -267,8 +377,9 @@ int oracle_drag(const double* T, int64_t n, int32_t m, double r, int64_t* out_id
     if (m < 3 || n < 2 * (int64_t)m) return OR_EINVAL;
     series_m s;
     if (series_m_init(&s, T, n, m, flat_eps_of(T, n)) != OR_OK) return OR_ENOMEM;
-    int rc = drag_core(&s, r, out_idx, out_nn, out_nnidx, out_count);
-    if (out_evals) *out_evals = s.evals;
+    uint64_t ev = 0;
+    int rc = drag_core(&s, r, out_idx, out_nn, out_nnidx, out_count, &ev);
+    if (out_evals) *out_evals = ev;
     series_m_free(&s);
     return rc;
 }
@@ -390,14 +501,13 @@ int oracle_merlin(const double* T, int64_t n, int32_t minL, int32_t maxL, int32_
         int64_t cnt = 0;
         for (;;) {
             ++ncall;
-            rc = drag_core(&s, r, d_idx, d_nn, d_nnidx, &cnt);
+            rc = drag_core(&s, r, d_idx, d_nn, d_nnidx, &cnt, &total_evals);
             if (rc != OR_OK) break;
             if (cnt >= k) break;
             if (mode == 0) r *= 0.5;
             else if (mode == 1) r *= 0.99;
             else r = (step > 0.0) ? r - step : 0.99 * r;
         }
-        total_evals += s.evals;
         series_m_free(&s);
         if (rc != OR_OK) break;
         for (int64_t a = 0; a < cnt; ++a) {

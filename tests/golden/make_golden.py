@@ -5,13 +5,21 @@ the float64 input series (regenerated from the seeded generator, never
 stored), and the oracle's MERLIN output.  The values come from the CPU
 oracle in ``oracle/merlin.c`` and nothing else.
 
-Usage:  python tests/golden/make_golden.py c1 [c2 ...]
+Usage:
+    python tests/golden/make_golden.py c1 [c2 c3 c5 ...]
+    python tests/golden/make_golden.py c4 [--jobs J] [--series 0,5,7]
+
+``c4`` writes one file per series of the 64-series batch under
+``tests/golden/c4/`` (the series are independent problems), J series at a
+time in separate processes; series whose file already exists are skipped.
 """
 
 from __future__ import annotations
 
 import json
+import multiprocessing
 import os
+import platform
 import sys
 import time
 
@@ -25,16 +33,30 @@ from paper_2304_01660_amd import synth  # noqa: E402
 CONFIGS = {
     "c1": synth.config1,
     "c2": synth.config2,
+    "c3": synth.config3,
     "c5": synth.config5,
 }
+C4_DIR = os.path.join(HERE, "c4")
 
 
-def write(tag: str) -> str:
-    w = CONFIGS[tag]()
+def _host():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model or platform.machine(), "threads_used": 1}
+
+
+def record(w):
     t0 = time.time()
     o = oracle.merlin(w.T, w.minL, w.maxL, w.k)
     dt = time.time() - t0
-    rec = {
+    return {
         "workload": w.name,
         "source": "oracle/merlin.c oracle_merlin (serial FP64 MERLIN + DRAG)",
         "n": w.n, "minL": w.minL, "maxL": w.maxL, "k": w.k,
@@ -47,13 +69,60 @@ def write(tag: str) -> str:
         "r": [float(v) for v in o["r"]],
         "evals": int(o["evals"]),
         "oracle_seconds": dt,
+        "oracle_host": _host(),
     }
+
+
+def write(tag: str) -> str:
+    w = CONFIGS[tag]()
+    rec = record(w)
     path = os.path.join(HERE, f"{tag}_{w.name}.json")
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     return path
 
 
+def c4_path(s: int, w) -> str:
+    return os.path.join(C4_DIR, f"{s:02d}_{w.name}.json")
+
+
+def _c4_one(s: int) -> str:
+    w = synth.config4()[s]
+    rec = record(w)
+    rec["series_index"] = s
+    path = c4_path(s, w)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(rec, f, indent=1)
+    os.replace(tmp, path)
+    return f"{path} {rec['oracle_seconds']:.1f}s"
+
+
+def write_c4(jobs: int, series=None):
+    os.makedirs(C4_DIR, exist_ok=True)
+    ws = synth.config4()
+    todo = [s for s in (series if series is not None else range(len(ws)))
+            if not os.path.exists(c4_path(s, ws[s]))]
+    # largest series first so the pool drains evenly
+    todo.sort(key=lambda s: -ws[s].n)
+    with multiprocessing.Pool(jobs) as pool:
+        for msg in pool.imap_unordered(_c4_one, todo):
+            print(msg, flush=True)
+
+
 if __name__ == "__main__":
-    for tag in sys.argv[1:]:
-        print(write(tag), flush=True)
+    args = sys.argv[1:]
+    jobs, series = 1, None
+    if "--jobs" in args:
+        i = args.index("--jobs")
+        jobs = int(args[i + 1])
+        del args[i:i + 2]
+    if "--series" in args:
+        i = args.index("--series")
+        series = [int(x) for x in args[i + 1].split(",")]
+        del args[i:i + 2]
+    for tag in args:
+        if tag == "c4":
+            write_c4(jobs, series)
+        else:
+            print(write(tag), flush=True)

@@ -256,3 +256,108 @@ def test_config1_golden_is_regenerable_and_matches_bruteforce():
     np.testing.assert_array_equal(b["idx"], np.array(g["idx"]))
     np.testing.assert_allclose(b["nn"], np.array(g["nn"]), rtol=1e-12)
     np.testing.assert_array_equal(b["nnidx"], np.array(g["nnidx"]))
+
+
+def _schedule_cases():
+    """c1, twenty small series with 8-12 lengths each, and eight noisy sine
+    waves whose period is much longer than the windows.  On the latter the
+    nearest-neighbour distances fall as m grows (a longer window of a slow
+    sine has a larger spread, so the same noise weighs less once
+    z-normalised), which makes the r rules of the later lengths fail and
+    retry."""
+    w = synth.config1()
+    yield "c1", w.T, w.minL, w.maxL, w.k
+    rng = np.random.default_rng(777)
+    for c in range(20):
+        kind = ("rw", "noise", "ecg")[c % 3]
+        minL = int(rng.integers(5, 13))
+        maxL = minL + int(rng.integers(7, 12))
+        n = int(rng.integers(3 * maxL + 40, 420))
+        k = (1, 2, 3)[c % 3]
+        yield f"s{c}", synth.small_random(2000 + c, n, kind), minL, maxL, k
+    for c in range(8):
+        g = np.random.default_rng(4000 + c)
+        t = np.arange(420, dtype=np.float64)
+        noise = (0.003, 0.01)[c % 2]
+        T = np.sin(2 * math.pi * t / 150 + g.uniform(0, 2 * math.pi)) + noise * g.standard_normal(420)
+        yield f"sine{c}", T, 8, 19, 2
+
+
+def test_r_schedule_follows_alg1_on_bruteforce_values():
+    """MERLIN's r per length and its DRAG call count follow Alg. 1's rules,
+    with every success or failure decided by the brute-force profile.
+
+    A DRAG call at range r finds #{i : P_m(i) >= r} discords (every row when
+    r <= 0); it fails while that is below k.  The rules (readings of Alg. 1):
+    at minL, r starts at 2 sqrt(minL) and halves after each failure; at the
+    next four lengths it starts at 0.99 times the previous length's k-th
+    largest P and is multiplied by 0.99 after each failure; later it starts
+    at mean - 2 std of the last five lengths' k-th values (population std)
+    and drops by that std after each failure (by 1 % when the std is 0).
+    The call count, every failed r, and the successful r are checked.
+    """
+    retried = set()
+    for name, T, minL, maxL, k in _schedule_cases():
+        o = oracle.merlin(T, minL, maxL, k)
+        kth = []
+        for li, m in enumerate(range(minL, maxL + 1)):
+            P, _ = bf.profile(T, m)
+            N = P.shape[0]
+
+            def found(r):
+                return N if r <= 0 else int(np.count_nonzero(P >= r))
+
+            if li == 0:
+                r = 2.0 * math.sqrt(minL)
+                lower = lambda r: 0.5 * r                       # noqa: E731
+            elif li <= 4:
+                r = 0.99 * kth[li - 1]
+                lower = lambda r: 0.99 * r                      # noqa: E731
+            else:
+                h = np.array(kth[li - 5:li])
+                mu, sd = float(h.mean()), float(h.std())
+                r = mu - 2.0 * sd
+                lower = (lambda r, sd=sd: r - sd) if sd > 0 else (lambda r: 0.99 * r)
+            calls = 1
+            while True:
+                # no row of P may sit on the boundary r (the count would be
+                # decided by rounding, not by the rule)
+                assert np.all(np.abs(P - r) > 1e-9 * max(1.0, abs(r))), (name, m, r)
+                if found(r) >= k:
+                    break
+                r = lower(r)
+                calls += 1
+                assert calls < 200, (name, m)
+            assert int(o["calls"][li]) == calls, (name, m, int(o["calls"][li]), calls)
+            if calls > 1:
+                retried.add(0 if li == 0 else (1 if li <= 4 else 2))
+            assert abs(float(o["r"][li]) - r) <= 1e-9 * max(1.0, abs(r)), (name, m, o["r"][li], r)
+            kth.append(float(np.sort(P)[::-1][k - 1]))
+            # the reported k-th value is the one the next length's rule reads
+            assert abs(float(o["nn"][li * k + k - 1]) - kth[-1]) <= 1e-12 * max(1.0, kth[-1])
+    # every rule's failure branch was exercised
+    assert retried == {0, 1, 2}, retried
+
+
+def test_openmp_build_matches_serial():
+    """The OpenMP build of the oracle (inner candidate loops split over
+    threads, used for the largest stored results) returns exactly what the
+    serial build returns: MERLIN on config 1, and DRAG at a range small
+    enough that hundreds of candidates stay alive, so the threaded branch of
+    both phases runs."""
+    w = synth.config1()
+    a = oracle.merlin(w.T, w.minL, w.maxL, w.k)
+    b = oracle.merlin(w.T, w.minL, w.maxL, w.k, threads=4)
+    for key in a:
+        np.testing.assert_array_equal(np.asarray(a[key]), np.asarray(b[key]), err_msg=key)
+    T = synth.small_random(77, 5000, "noise")
+    P, _ = bf.profile(T, 16)
+    Ps = np.sort(P)[::-1]
+    r = float(0.5 * (Ps[600] + Ps[601]))    # between two rows: no rounding-decided boundary
+    s = oracle.drag(T, 16, r)
+    p = oracle.drag(T, 16, r, threads=4)
+    assert s[0].shape[0] > 256          # the candidate list passed the threading threshold
+    for x, y in zip(s[:3], p[:3]):
+        np.testing.assert_array_equal(x, y)
+    assert s[3] == p[3]
+    np.testing.assert_array_equal(s[0], np.nonzero(P >= r)[0])
