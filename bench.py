@@ -1,23 +1,28 @@
 """Benchmark: top-k range discords over a length range on one MI355X.
 
-Workload (one "step" = one full search, every length, through the C ABI):
-a seeded random walk of n = 100,000 points (FP32-canonical values) with five
-injected sine bursts or level shifts; lengths m = 64..128 (65 lengths),
-top-3 discords per length; FP32 selection sweep, FP64 refinement and exact
-FP64 distances.  Inputs are resident in HBM before the timed region.
+Headline workload (one "step" = one full search, every length, through the
+C ABI): a seeded ECG-like series of n = 1,000,000 points (beats of three
+Gaussian bumps, period U(240, 260) samples, N(0, 0.05^2) noise, 20 malformed
+beats; FP32-canonical values), lengths m = 128..256 (129 lengths), top-3
+discords per length; FP32 selection sweep, FP64 refinement and exact FP64
+distances.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: lengths/s as `value`, plus device-counted distance
 evaluations/s, the roofline of the dominant kernel (from HIP events recorded
-around its launches during the timed steps) and the CPU oracle on a bounded
-sample of the same workload.
+around its launches on the library's stream during instrumented steps), the
+per-length statistics kernel against the HBM roofline, legs on the other
+workloads (the 100k random walk, the 64-series batch against the plain
+per-series loop, forward + backward on the 200k random walk, the discord
+heatmap and the dense matrix profile) and the CPU oracle on a bounded sample
+of the headline workload.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
-import platform
 import sys
 import time
 
@@ -27,41 +32,199 @@ sys.path.insert(0, ROOT)
 METRIC = "z-norm distance evals/sec + lengths/sec over [minL,maxL]; batched vs plain"
 # VALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-ops/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 # Minimal VALU lane-operations per pair evaluation of a sweep step: two FMAs
 # for the covariance update, one multiply by 1/(sqrt(m) sigma_j), one compare
 # (selection) or max (refinement).
 OPS_PER_EVAL = 4
+# Algorithmic HBM bytes of the per-length statistics step per subsequence
+# and length: the series value (8), mean and sigma read and written (32),
+# three FP32 helpers (12), two bitmaps (1/4, rounded into the 52).
+LENGTH_BYTES_PER_SUBSEQ = 52
 KERNEL_NAMES = {
     "select_near": "k_select_near",
     "select_far": "k_select_far",
     "refine": "k_refine",
     "polish": "k_polish",
+    "length": "k_length",
+}
+CLASS_NAMES = ("select_near", "select_far", "refine", "polish", "length")
+SERIES_TEXT = {
+    "c2": "seeded random walk with 5 injected sine bursts/level shifts (seed 1)",
+    "c3": ("seeded ECG-like beat train (3 Gaussian bumps per beat, period U(240, 260), "
+           "N(0, 0.05^2) noise) with 20 malformed beats (seed 2)"),
+    "c5": "seeded random walk with 10 injected sine bursts (seed 4)",
 }
 
 
-def cpu_baseline(w, golden, n_lengths: int):
-    """Time the oracle's range search at MERLIN's final r for a few lengths."""
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model or "unknown", "logical_cpus": os.cpu_count()}
+
+
+def workload(synth, tag):
+    return {"c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[tag]()
+
+
+def golden_of(tag, w):
+    path = os.path.join(ROOT, "tests", "golden", f"{tag}_{w.name}.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def cpu_baseline(w, golden, budget_s: float):
+    """The oracle's DRAG (serial, FP64) at MERLIN's own final r for lengths
+    spread over the range, until the time budget is spent.  At each of these
+    lengths the oracle's MERLIN made exactly one DRAG call (recorded in the
+    stored result), so the sample is that part of its run; the first length's
+    r search (several DRAG calls) is not sampled, and the full run's own
+    wall time is reported beside it."""
     import oracle
 
     if golden is None:
         return None
     L = w.maxL - w.minL + 1
-    picks = [int(round(x)) for x in
-             [1 + i * (L - 2) / max(1, n_lengths - 1) for i in range(n_lengths)]]
+    single = [li for li in range(1, L) if golden["calls"][li] == 1]
+    # stratified order: middle, then halves, quarters, ...
+    order, seen = [], set()
+    for step in (2, 4, 8, 16, 32, 64, 128):
+        for q in range(1, step, 2):
+            li = single[min(len(single) - 1, q * len(single) // step)]
+            if li not in seen:
+                seen.add(li)
+                order.append(li)
     t0 = time.perf_counter()
-    for li in picks:
-        m = w.minL + li
-        oracle.drag(w.T, m, golden["r"][li])
+    done = []
+    for li in order:
+        oracle.drag(w.T, w.minL + li, golden["r"][li])
+        done.append(w.minL + li)
+        if time.perf_counter() - t0 >= budget_s:
+            break
     dt = time.perf_counter() - t0
+    full_s = golden.get("oracle_seconds")
     return {
-        "value": len(picks) / dt,
+        "value": len(done) / dt,
         "unit": "lengths/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"serial FP64 DRAG of the oracle at MERLIN's final r for lengths "
-                   f"{[w.minL + li for li in picks]} of the same series ({dt:.1f} s); excludes "
-                   f"the first length's r-halving rounds (about 300 s alone for the oracle)"),
-        "host_cpu": platform.processor() or platform.machine(),
+        "sample": (f"serial FP64 DRAG of the oracle (oracle/merlin.c) at MERLIN's final r for "
+                   f"lengths {done} of the same series, {dt:.1f} s; MERLIN made one DRAG call at "
+                   f"each of them; the first length's r search is not in the sample"),
+        "host_cpu": host_cpu(),
+        "full_run": {
+            "seconds": full_s,
+            "lengths_per_s": (L / full_s) if full_s else None,
+            "what": "the oracle's complete MERLIN on this workload (every length, every DRAG "
+                    "call), timed when the stored result was written",
+            "host_cpu": (golden.get("oracle_host") or {}).get("cpu"),
+            "threads": (golden.get("oracle_host") or {}).get("threads_used", 1),
+        },
+    }
+
+
+def check_golden(out, golden):
+    import numpy as np
+    if golden is None:
+        return "no-golden"
+    idx = out["idx"].cpu().numpy()
+    nn = out["nn_dist"].cpu().numpy()
+    gi = np.array(golden["idx"])
+    gn = np.array(golden["nn"])
+    if not np.allclose(nn, gn, rtol=1e-9):
+        return "nn-mismatch"
+    if not np.array_equal(idx, gi):
+        return "index-near-tie"
+    return "exact"
+
+
+def search_leg(api, torch, dev, w, tuned, steps, warmup):
+    """Time the full search (production path: graph replay, no events), then
+    the same steps with HIP events around every kernel class on the
+    library's stream."""
+    T = torch.from_numpy(w.T).to(dev)
+    L = w.maxL - w.minL + 1
+    ws = torch.empty(api.workspace_size(w.n, w.minL, w.maxL, w.k), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        api.discords(T, w.minL, w.maxL, w.k, workspace=ws, **tuned)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True, **tuned)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / steps * 1e3
+    st_prod = out["stats"]
+    agg = None
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        out_t = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True,
+                             time_kernels=True, **tuned)
+        st = out_t["stats"]
+        if agg is None:
+            agg = {k: (list(v) if isinstance(v, list) else v) for k, v in st.items()}
+        else:
+            for k, v in st.items():
+                if isinstance(v, list):
+                    agg[k] = [a + b for a, b in zip(agg[k], v)]
+                else:
+                    agg[k] += v
+    torch.cuda.synchronize()
+    ms_instrumented = (time.perf_counter() - t1) / steps * 1e3
+    for key in ("idx", "nn_dist", "nn_idx", "count"):
+        if not torch.equal(out[key], out_t[key]):
+            raise SystemExit("instrumented and production runs disagree")
+    evals = st_prod["evals_select"] + st_prod["evals_refine"] + st_prod["evals_polish"]
+    kernels = {}
+    for ci, name in enumerate(CLASS_NAMES):
+        launches = agg["kernel_launches"][ci]
+        ms = agg["kernel_ms"][ci]
+        kernels[name] = {
+            "launches_per_step": launches / steps,
+            "ms_per_step": ms / steps,
+            "evals_per_step": agg["kernel_evals"][ci] / steps,
+            "avg_launch_us": (ms / launches * 1e3) if launches else None,
+        }
+    dom = max(("select_near", "select_far", "refine"), key=lambda k: kernels[k]["ms_per_step"])
+    dk = kernels[dom]
+    achieved = None
+    if dk["ms_per_step"] > 0:
+        # evals per launch / average launch duration == evals / summed duration
+        achieved = dk["evals_per_step"] * OPS_PER_EVAL / (dk["ms_per_step"] * 1e-3) / 1e12
+    # per-length statistics kernel against HBM: algorithmic bytes of every
+    # length's statistics over the kernel's summed time (retry rounds only
+    # reset bitmaps and add time, not algorithmic bytes)
+    lk = kernels["length"]
+    len_bytes = sum(LENGTH_BYTES_PER_SUBSEQ * (w.n - m + 1) for m in range(w.minL, w.maxL + 1))
+    len_gbps = len_bytes / (lk["ms_per_step"] * 1e-3) / 1e9 if lk["ms_per_step"] > 0 else None
+    return {
+        "out": out,
+        "T": T,
+        "ms_per_step": ms_per_step,
+        "seconds": dt,
+        "lengths_per_s": L / (ms_per_step * 1e-3),
+        "evals_per_s": evals / (ms_per_step * 1e-3),
+        "range_searches_per_step": st_prod["range_searches"],
+        "ms_per_step_instrumented": ms_instrumented,
+        "kernels": kernels,
+        "dominant": dom,
+        "achieved": achieved,
+        "length_kernel_hbm": {
+            "bytes_per_step": len_bytes,
+            "ms_per_step": lk["ms_per_step"],
+            "launches_per_step": lk["launches_per_step"],
+            "achieved_GBps": len_gbps,
+            "peak_GBps": HBM_PEAK_GBPS,
+            "frac": len_gbps / HBM_PEAK_GBPS if len_gbps else None,
+            "bytes_per_subsequence": LENGTH_BYTES_PER_SUBSEQ,
+        },
     }
 
 
@@ -81,7 +244,7 @@ def batched_vs_plain(api, synth, tuning, torch, dev, reps: int, retune: bool):
     wsb = torch.empty(nb, dtype=torch.uint8, device=dev)
     flat = torch.cat(vals)
     sizes = [v.shape[0] for v in vals]
-    tuned, report = tuning.options(tuning.BATCH_NAME), "stored"
+    tuned, report = tuning.batch_options(), "stored"
     if retune:
         probe, treps = tuning.PROBES["batch"]
         tuned, report = api.autotune(vals, lo, hi, 1, probe_lengths=probe, reps=treps)
@@ -225,19 +388,51 @@ def measured_traffic(kernel: str, workload: str, options: dict):
     return None, None
 
 
-def check_golden(out, golden, T):
+def grad_leg(api, torch, dev, synth, tuning, reps: int = 3):
+    """Forward + backward on the 200k random walk (m 96..160, top-5): the
+    search, then the gradient of sum_q w_q nnDist_q with respect to the
+    series (w ~ N(0, 1), seed 5) through the adjoint kernels, each timed
+    with events on the caller's stream (the library orders its own stream
+    inside the call)."""
     import numpy as np
-    if golden is None:
-        return "no-golden"
-    idx = out["idx"].cpu().numpy()
-    nn = out["nn_dist"].cpu().numpy()
-    gi = np.array(golden["idx"])
-    gn = np.array(golden["nn"])
-    if not np.allclose(nn, gn, rtol=1e-9):
-        return "nn-mismatch"
-    if not np.array_equal(idx, gi):
-        return "index-near-tie"
-    return "exact"
+
+    w = synth.config5()
+    L = w.maxL - w.minL + 1
+    T = torch.from_numpy(w.T).to(dev)
+    opts = tuning.options_for(w.n, w.minL, w.maxL)
+    wts = torch.from_numpy(np.random.default_rng(5).standard_normal(L * w.k)).to(dev)
+    out = api.discords(T, w.minL, w.maxL, w.k, **opts)
+    api.discords_backward(T, out["idx"], out["len"], wts, maxm=w.maxL)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    for _ in range(reps):
+        ev[0].record(st)
+        out = api.discords(T, w.minL, w.maxL, w.k, **opts)
+        ev[1].record(st)
+        api.discords_backward(T, out["idx"], out["len"], wts, maxm=w.maxL)
+        ev[2].record(st)
+        torch.cuda.synchronize()
+        fwd += ev[0].elapsed_time(ev[1])
+        bwd += ev[1].elapsed_time(ev[2])
+    fwd /= reps
+    bwd /= reps
+    lens = out["len"].cpu().numpy().astype(np.int64)
+    # the adjoint recomputes every reported row against every column: one
+    # FP64 fused multiply-add per window element and pair (the centred dot
+    # product), the column's own statistics besides
+    flops = float(sum(2.0 * m * (w.n - m + 1) for m in lens))
+    return {
+        "workload": w.name,
+        "forward_ms": fwd,
+        "backward_ms": bwd,
+        "lengths_per_s_fwd_bwd": L / ((fwd + bwd) * 1e-3),
+        "rows": int(lens.shape[0]),
+        "backward_pair_flops": flops,
+        "backward_TFLOPs": flops / (bwd * 1e-3) / 1e12,
+        "backward_frac_fp64_peak": flops / (bwd * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+    }
 
 
 def main():
@@ -245,19 +440,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=("c2", "c3", "c5"),
+                    help="headline workload (default: the million-point ECG-like series)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-lengths", type=int, default=12)
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work in the CPU baseline sample")
+    ap.add_argument("--no-legs", action="store_true", help="headline workload only")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-heatmap", action="store_true",
+                    help="skip the discord heatmap / interest leg")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense matrix-profile leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (a known-size "
                          "reference for hardware traffic counters) and exit")
     ap.add_argument("--retune", action="store_true",
                     help="run the autotuner now instead of using the stored tile options")
     ap.add_argument("--batch-reps", type=int, default=2)
-    ap.add_argument("--no-heatmap", action="store_true",
-                    help="skip the discord heatmap / interest leg")
-    ap.add_argument("--no-dense", action="store_true",
-                    help="skip the dense matrix-profile leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
@@ -278,73 +478,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 8}), flush=True)
         return 0
-    w = synth.config2()
+    w = workload(synth, args.workload)
     L = w.maxL - w.minL + 1
-    gpath = os.path.join(ROOT, "tests", "golden", "c2_rw100k_m64-128_k3_fp32.json")
-    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
-    T = torch.from_numpy(w.T).to(dev)
-    ws = torch.empty(api.workspace_size(w.n, w.minL, w.maxL, w.k), dtype=torch.uint8, device=dev)
+    golden = golden_of(args.workload, w)
     # tile geometry chosen by the autotuner (stored, or tuned now, untimed)
-    tuned, tune_report = tuning.options(w.name), "stored"
+    tuned, tune_report = tuning.options_for(w.n, w.minL, w.maxL), "stored"
     if args.retune:
         probe, treps = tuning.PROBES["single"]
-        tuned, tune_report = api.autotune(T, w.minL, w.maxL, w.k, probe_lengths=probe, reps=treps)
-    for _ in range(args.warmup):
-        api.discords(T, w.minL, w.maxL, w.k, workspace=ws, **tuned)
-    torch.cuda.synchronize()
-
-    # timed region: the production path (round graphs replayed, no events)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True, **tuned)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    st_prod = out["stats"]
-
-    # the same steps again with HIP events around every sweep launch, on the
-    # library's stream where the kernels run: per-kernel device time
-    agg = None
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        out_t = api.discords(T, w.minL, w.maxL, w.k, workspace=ws, return_stats=True,
-                             time_kernels=True, **tuned)
-        st = out_t["stats"]
-        if agg is None:
-            agg = {k: (list(v) if isinstance(v, list) else v) for k, v in st.items()}
-        else:
-            for k, v in st.items():
-                if isinstance(v, list):
-                    agg[k] = [a + b for a, b in zip(agg[k], v)]
-                else:
-                    agg[k] += v
-    torch.cuda.synchronize()
-    ms_instrumented = (time.perf_counter() - t1) / args.steps * 1e3
-    for key in ("idx", "nn_dist", "nn_idx", "count"):
-        if not torch.equal(out[key], out_t[key]):
-            raise SystemExit("instrumented and production runs disagree")
-    parity = check_golden(out, golden, w.T)
-
-    evals = (st_prod["evals_select"] + st_prod["evals_refine"] + st_prod["evals_polish"]) * args.steps
-    kernels = {}
-    for ci, name in enumerate(("select_near", "select_far", "refine", "polish")):
-        launches = agg["kernel_launches"][ci]
-        ms = agg["kernel_ms"][ci]
-        kernels[name] = {
-            "launches_per_step": launches / args.steps,
-            "ms_per_step": ms / args.steps,
-            "evals_per_step": agg["kernel_evals"][ci] / args.steps,
-            "avg_launch_us": (ms / launches * 1e3) if launches else None,
-        }
-    dom = max(("select_near", "select_far", "refine"), key=lambda k: kernels[k]["ms_per_step"])
-    dk = kernels[dom]
-    achieved = None
-    if dk["ms_per_step"] > 0:
-        # evals per launch / average launch duration == evals / summed duration
-        achieved = dk["evals_per_step"] * OPS_PER_EVAL / (dk["ms_per_step"] * 1e-3) / 1e12
-    traffic, traffic_src = measured_traffic(KERNEL_NAMES[dom], w.name, tuned)
+        tuned, tune_report = api.autotune(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, w.k,
+                                          probe_lengths=probe, reps=treps)
+    head = search_leg(api, torch, dev, w, tuned, args.steps, args.warmup)
+    parity = check_golden(head["out"], golden)
+    dk = head["kernels"][head["dominant"]]
+    achieved = head["achieved"]
+    traffic, traffic_src = measured_traffic(KERNEL_NAMES[head["dominant"]], w.name, tuned)
     roofline = {
         "bound": "alu",
         "achieved": achieved,
@@ -354,33 +501,59 @@ def main():
         "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM, counter-measured)",
         "traffic_source": traffic_src,
-        "kernel": KERNEL_NAMES[dom],
+        "kernel": KERNEL_NAMES[head["dominant"]],
         "ops_per_eval": OPS_PER_EVAL,
         "avg_launch_us": dk["avg_launch_us"],
         "evals_per_launch": (dk["evals_per_step"] / dk["launches_per_step"]
                              if dk["launches_per_step"] else None),
+        "frac_of_fp32_peak": (achieved * 2 / 157.3) if achieved else None,
     }
-    batched = None
-    if not args.no_batched:
-        batched = batched_vs_plain(api, synth, tuning, torch, dev, args.batch_reps, args.retune)
-    heat = None
-    if not args.no_heatmap:
-        heat = heatmap_leg(api, torch, dev, w, T, tuned, ms_per_step, out)
-    dense = None
-    if not args.no_dense:
-        dense = dense_leg(api, torch, w, T, tuned, ms_per_step)
+    legs = {}
+    if not args.no_legs:
+        if args.workload != "c2":
+            w2 = synth.config2()
+            leg = search_leg(api, torch, dev, w2, tuning.options_for(w2.n, w2.minL, w2.maxL),
+                             max(5, args.steps), 1)
+            d2 = leg["kernels"][leg["dominant"]]
+            legs["rw100k"] = {
+                "workload": w2.name,
+                "lengths_per_s": leg["lengths_per_s"],
+                "ms_per_step": leg["ms_per_step"],
+                "evals_per_s": leg["evals_per_s"],
+                "parity_vs_oracle": check_golden(leg["out"], golden_of("c2", w2)),
+                "dominant_kernel": KERNEL_NAMES[leg["dominant"]],
+                "dominant_avg_launch_us": d2["avg_launch_us"],
+                "dominant_frac_valu": (leg["achieved"] / VALU_PEAK_TOPS) if leg["achieved"] else None,
+                "length_kernel_hbm_frac": leg["length_kernel_hbm"]["frac"],
+                "kernels": leg["kernels"],
+            }
+            plain2 = leg
+        else:
+            w2, plain2 = w, head
+        if not args.no_batched:
+            legs["batched"] = batched_vs_plain(api, synth, tuning, torch, dev, args.batch_reps,
+                                               args.retune)
+        if not args.no_grad:
+            legs["fwd_bwd"] = grad_leg(api, torch, dev, synth, tuning)
+        opts2 = tuning.options_for(w2.n, w2.minL, w2.maxL)
+        if not args.no_heatmap:
+            legs["heatmap"] = heatmap_leg(api, torch, dev, w2, plain2["T"], opts2,
+                                          plain2["ms_per_step"], plain2["out"])
+        if not args.no_dense:
+            legs["dense_matrix_profile"] = dense_leg(api, torch, w2, plain2["T"], opts2,
+                                                     plain2["ms_per_step"])
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, golden, args.cpu_lengths)
+        cpu = cpu_baseline(w, golden, args.cpu_budget)
 
     line = {
         "metric": METRIC,
-        "value": L / (ms_per_step * 1e-3),
+        "value": head["lengths_per_s"],
         "unit": "lengths/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -389,19 +562,18 @@ def main():
         "config": {
             "workload": w.name,
             "n": w.n, "minL": w.minL, "maxL": w.maxL, "k": w.k, "lengths": L,
-            "series": "seeded random walk with 5 injected sine bursts/level shifts (seed 1)",
+            "series": SERIES_TEXT[args.workload],
             "tile_options": tuned or "defaults",
         },
         "tune_report": tune_report,
-        "evals_per_s": evals / dt,
-        "range_searches_per_step": st_prod["range_searches"],
-        "ms_per_step_instrumented": ms_instrumented,
-        "kernels": kernels,
+        "evals_per_s": head["evals_per_s"],
+        "range_searches_per_step": head["range_searches_per_step"],
+        "ms_per_step_instrumented": head["ms_per_step_instrumented"],
+        "kernels": head["kernels"],
+        "length_kernel_hbm": head["length_kernel_hbm"],
         "parity_vs_oracle": parity,
         "roofline": roofline,
-        "batched": batched,
-        "heatmap": heat,
-        "dense_matrix_profile": dense,
+        "legs": legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -89,7 +89,8 @@ enum {
     PALMAD_KERNEL_SELECT_FAR = 1,  /* split selection pass over the remaining columns */
     PALMAD_KERNEL_REFINE = 2,      /* refinement pass (exact FP64 nearest neighbour) */
     PALMAD_KERNEL_POLISH = 3,      /* direct FP64 distances of the top candidates */
-    PALMAD_KERNEL_CLASSES = 4
+    PALMAD_KERNEL_LENGTH = 4,      /* per-length statistics, helpers and round resets */
+    PALMAD_KERNEL_CLASSES = 5
 };
 
 /* Per-call counters (host struct, filled when the call returns). */

@@ -50,9 +50,9 @@ class Stats(ctypes.Structure):
         ("range_searches", ctypes.c_uint64),
         ("survivors", ctypes.c_uint64),
         ("seconds", ctypes.c_double),
-        ("kernel_evals", ctypes.c_uint64 * 4),
-        ("kernel_launches", ctypes.c_uint64 * 4),
-        ("kernel_ms", ctypes.c_double * 4),
+        ("kernel_evals", ctypes.c_uint64 * 5),
+        ("kernel_launches", ctypes.c_uint64 * 5),
+        ("kernel_ms", ctypes.c_double * 5),
         ("rows_after_near", ctypes.c_uint64),
         ("rows_after_far", ctypes.c_uint64),
     ]

@@ -65,6 +65,7 @@ struct Ctrl {
     int32_t nonfinite; // set when the series holds NaN/Inf
     double flat_eps;   // sigma threshold of a flat window
     double sigmaT;     // population sigma of the whole series
+    double gam2;       // squared local sigma contrast at the current length (FP32 guard)
     int64_t flat_min, flat_max;   // smallest/largest flat window index at m (or -1)
     uint32_t nhot;     // entries of SeriesDev::hot (set by k_round_end)
     int32_t hot_r;     // tile height the hot list was built for
@@ -116,6 +117,7 @@ struct SeriesDev {
     double* hist;        // nnDist history per length [L]
     unsigned long long* evc;  // pair evaluations [EV_CLASSES][EV_SLOTS]
     double* red;         // reduction scratch [2 * RED_BLOCKS]
+    double* sgm;         // per block of 256 windows: largest, smallest sigma [2 * blocks]
     Ctrl* ctrl;
     // outputs (rows of this series; NULL for a bare range search)
     int64_t* idx;
@@ -135,7 +137,8 @@ struct Layout {
     int64_t n, Nmax, Npad, Tlen, nwords, npart;
     int32_t minL, maxL, k, L, kp;
     size_t off_T, off_mu, off_var, off_mu2, off_var2, off_h32, off_h64, off_alive, off_rho, off_rhs, off_unc,
-        off_tsel, off_tref, off_hot, off_twork, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red, total;
+        off_tsel, off_tref, off_hot, off_twork, off_cand, off_part, off_xc, off_hist, off_evc, off_ctrl, off_red,
+        off_sgm, total;
 };
 bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out);
 SeriesDev carve(void* base, const Layout& lay);
@@ -162,7 +165,7 @@ struct Batch {
 };
 
 // Optional per-kernel event timing (host side).
-constexpr int KCLASSES = 4;  // select near, select far, refine, polish
+constexpr int KCLASSES = 5;  // select near, select far, refine, polish, per-length statistics
 struct KernelTimer {
     bool on;
     hipEvent_t ev[KCLASSES][2];

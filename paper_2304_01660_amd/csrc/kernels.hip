@@ -166,6 +166,35 @@ __device__ __forceinline__ unsigned long long pair_count(long long ilo, long lon
 // this round, its pruning threshold and reset the round's work counters.
 // rem[0] (series with work left after the round, counted by k_round_end) and
 // rem[1] (series that gave up, now or in an earlier round) start at zero here.
+// Guard band of the FP32 selection sweep.  An FP32 correlation drifts from
+// the exact one by rounding: the centred recurrence accumulates one rounding
+// of the covariance per step over chains of at most R_MAX - 1 steps, and a
+// pair's covariance is divided by m sigma_i sigma_j, so windows with a small
+// spread next to windows with a large one (within the R_MAX windows a chain
+// passes) amplify the covariance's absolute error.  With gamma the largest
+// ratio of the nearby largest spread to a window's own spread, the drift
+// measured over the configured workloads stays below
+//     2^-24 * sqrt(R_MAX) * gamma^2 / 2
+// (random walks, ECG-like series); the band is twice that, and never below
+// the caller's guard.  A series with an extreme spread contrast thus gets a
+// wide band (the selection sweep prunes less, the FP64 refinement decides),
+// never an unsound one.
+constexpr double GUARD_PER_CONTRAST2 = 2.0 * 0x1p-24 * 22.62741699796952;  // 2 u sqrt(512)
+
+__device__ __forceinline__ double sel_guard(const Ctrl* c, float guard)
+{
+    if (guard <= 0.0f) return 0.0;  // FP64 selection sweep: no band
+    const double gc = GUARD_PER_CONTRAST2 * c->gam2;
+    return gc > (double)guard ? gc : (double)guard;
+}
+
+__device__ __forceinline__ void set_sel_thresholds(Ctrl* c, float guard)
+{
+    c->thr_sel = c->thr64 + sel_guard(c, guard);
+    // round up: an FP32 threshold must never prune more than thr_sel
+    c->thr32 = __double2float_ru(c->thr_sel);
+}
+
 __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
 {
     const int li = c->li;
@@ -194,9 +223,10 @@ __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
     const double r = c->r;
     c->prune = r > 0.0 ? 1 : 0;
     c->thr64 = r > 0.0 ? 1.0 - r * r / (2.0 * (double)m) : 2.0;
-    c->thr_sel = c->thr64 + (double)guard;
-    // round up: an FP32 threshold must never prune more than thr_sel
-    c->thr32 = __double2float_ru(c->thr_sel);
+    // a new length's contrast is measured by k_length and k_guard, which
+    // then resets the selection thresholds; a repeat keeps the current length's
+    if (c->new_len) c->gam2 = 0.0;
+    set_sel_thresholds(c, guard);
     c->nlive_sel = c->maxc_sel = 0;
     c->nlive_ref = c->maxc_ref = 0;
     c->ctr_sel = c->ctr_ref = 0ull;
@@ -305,17 +335,83 @@ __device__ __forceinline__ void grow_stats(const double* __restrict__ T, int64_t
     var = dm / (dm + 1.0) * (v0 + d * d / (dm + 1.0));
 }
 
+// Block extremes of the window spreads (every block of k_length at a new
+// length): the largest and smallest sigma of the block's non-flat windows.
+__device__ void spread_extremes(const SeriesDev& s, int64_t lb, double smax, double smin)
+{
+    __shared__ double rmax[4], rmin[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        smax = fmax(smax, __shfl_xor(smax, o));
+        smin = fmin(smin, __shfl_xor(smin, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        rmax[w] = smax;
+        rmin[w] = smin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = rmax[0], z = rmin[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+            a = fmax(a, rmax[q]);
+            z = fmin(z, rmin[q]);
+        }
+        s.sgm[2 * lb] = a;
+        s.sgm[2 * lb + 1] = z;
+    }
+}
+
+// The spread contrast of a new length and the round's selection thresholds
+// (one block per series, after k_length): over every block of 256 windows,
+// the largest spread of the two blocks on either side (a superset of the
+// R_MAX - 1 windows a recurrence chain passes on each side) over the block's
+// smallest spread, squared (see sel_guard).
+constexpr int GUARD_BLOCK = 1024;
+__global__ __launch_bounds__(GUARD_BLOCK) void k_guard(SeriesDev* S, float guard)
+{
+    const SeriesDev& s = S[blockIdx.x];
+    Ctrl* c = s.ctrl;
+    if (!c->active || !c->new_len || guard <= 0.0f) return;
+    __shared__ double red[GUARD_BLOCK / 64];
+    const int64_t nb = (s.n - c->m + 1 + 255) / 256;
+    double g = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
+        const double lo = s.sgm[2 * q + 1];
+        double hi = 0.0;
+        for (int64_t e = (q >= 2 ? q - 2 : 0); e <= q + 2 && e < nb; ++e) hi = fmax(hi, s.sgm[2 * e]);
+        if (lo < f_inf<double>()) {  // not a block of flat windows only
+            const double rt = hi / lo;
+            g = fmax(g, rt * rt);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) g = fmax(g, __shfl_xor(g, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < GUARD_BLOCK / 64; ++q) g = fmax(g, red[q]);
+        c->gam2 = g;
+        set_sel_thresholds(c, guard);
+    }
+}
+
 // df[i] = (t_{i+m} - t_i)/2, dg[i] = (t_{i+m} - mu_{i+1}) + (t_i - mu_i) for
 // i < N-1 (zero beyond), inv[i] = 1/(sqrt(m) sigma_i) for non-flat i < N.
+//
+// At a new length every block also records the largest and smallest window
+// sigma of its 256 windows, from which k_guard sets the FP32 guard band.
 __global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
 {
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
-    const int64_t i = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t lb = blockIdx.x - pfx[b];
+    const int64_t i = lb * (int64_t)blockDim.x + threadIdx.x;
     const int32_t m = c->m;
     const int64_t N = s.n - m + 1;
+    double smax = 0.0, smin = f_inf<double>();  // spread extremes of this thread's window
     if (c->new_len && i < s.Npad + 64) {
         const double* __restrict__ T = s.T;
         const bool odd = (c->li & 1) != 0;
@@ -348,6 +444,7 @@ __global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
                 atomicMax((long long*)&c->flat_max, (long long)i);
             } else {
                 inv = 1.0 / (sqrt((double)m) * sg);
+                smax = smin = sg;
             }
         }
         s.df64[i] = df;
@@ -357,6 +454,7 @@ __global__ void k_length(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
         s.dg32[i] = (float)dg;
         s.inv32[i] = (float)inv;
     }
+    if (c->new_len) spread_extremes(s, lb, smax, smin);
     // every round: all N subsequences start alive, row maxima at -inf
     if (i < s.nwords) {
         const int64_t lo = i * 64;
@@ -2094,7 +2192,10 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
     const unsigned int elem = (unsigned int)total[PFX_ELEM];
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(256), 0, st, bt.s, bt.B, cfg.guard,
                        bt.remaining);
+    cfg.timer->begin(4, st);
     hipLaunchKernelGGL(k_length, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
+    cfg.timer->end(4, st);
+    hipLaunchKernelGGL(k_guard, dim3(bt.B), dim3(GUARD_BLOCK), 0, st, bt.s, cfg.guard);
     if (cfg.dist_bits == 64) launch_select<double>(bt, cfg, total, st);
     else launch_select<float>(bt, cfg, total, st);
     switch (cfg.q_ref) {
@@ -2386,6 +2487,7 @@ bool make_layout(int64_t n, int32_t minL, int32_t maxL, int32_t k, Layout* out)
     l.off_evc = o;   o = al256(o + sizeof(unsigned long long) * EV_CLASSES * EV_SLOTS);
     l.off_ctrl = o;  o = al256(o + sizeof(Ctrl));
     l.off_red = o;   o = al256(o + sizeof(double) * 2 * RED_BLOCKS);
+    l.off_sgm = o;   o = al256(o + sizeof(double) * 2 * (size_t)((l.Npad + 64 + 255) / 256));
     l.total = o;
     *out = l;
     return true;
@@ -2433,6 +2535,7 @@ SeriesDev carve(void* base, const Layout& l)
     s.evc = (unsigned long long*)(p + l.off_evc);
     s.ctrl = (Ctrl*)(p + l.off_ctrl);
     s.red = (double*)(p + l.off_red);
+    s.sgm = (double*)(p + l.off_sgm);
     return s;
 }
 

@@ -10,6 +10,7 @@ import math
 
 import numpy as np
 
+import oracle
 from oracle import bruteforce as bf
 
 REL = 1e-9
@@ -47,3 +48,34 @@ def check_against_profiles(T, out, minL, maxL, k, rel=REL):
             Zj = (T[j:j + m] - T[j:j + m].mean()) / T[j:j + m].std()
             d = math.sqrt(((Zg - Zj) ** 2).sum())
             assert abs(d - P[g]) <= 1e-7 * max(1.0, P[g]), (m, q, j, J[g], d, P[g])
+
+
+def match_rows(T, out, g, rel=REL):
+    """Every row of a search result against a stored oracle result."""
+    idx = out["idx"].cpu().numpy()
+    ln = out["len"].cpu().numpy()
+    nn = out["nn_dist"].cpu().numpy()
+    nnj = out["nn_idx"].cpu().numpy()
+    cnt = out["count"].cpu().numpy()
+    gi = np.array(g["idx"])
+    gn = np.array(g["nn"])
+    gj = np.array(g["nnidx"])
+    k = g["k"]
+    assert idx.shape == gi.shape
+    np.testing.assert_array_equal(ln, np.array(g["len"]))
+    assert np.all(cnt >= k)
+    ties = 0
+    for q in range(gi.shape[0]):
+        m = g["minL"] + q // k
+        if idx[q] == gi[q]:
+            assert nnj[q] == gj[q], (q, m, idx[q], nnj[q], gj[q])
+        else:
+            # near tie: the oracle's exact distance of the reported row
+            d, j = oracle.nn_row(T, m, int(idx[q]))
+            assert abs(d - gn[q]) <= rel * max(1.0, gn[q]), (q, idx[q], gi[q], d, gn[q])
+            assert nnj[q] == j, (q, nnj[q], j)
+            ties += 1
+        assert abs(idx[q] - nnj[q]) >= m
+        assert 0 < nn[q] <= 2 * math.sqrt(m) + 1e-12
+    np.testing.assert_allclose(nn, gn, rtol=rel)
+    return ties

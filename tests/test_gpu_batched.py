@@ -9,7 +9,9 @@ workload is checked against the single-series path for every series and
 against the oracle's exact nearest-neighbour distance on sampled rows.
 """
 
+import json
 import math
+import os
 import sys
 
 import numpy as np
@@ -17,7 +19,7 @@ import pytest
 
 import oracle
 from paper_2304_01660_amd import synth
-from parity_helpers import check_against_profiles
+from parity_helpers import check_against_profiles, match_rows
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -121,38 +123,35 @@ def test_batched_nonfinite_names_the_series():
 
 
 def test_config4_batched_full_size():
-    """The 64-series workload: identical to 64 single-series calls; sampled
-    rows match the oracle's exact nearest neighbour; sampled rows never
-    beat the reported top-1."""
+    """The 64-series workload in one batched call, in the tile geometry the
+    benchmark times: every row of every series against the oracle's stored
+    MERLIN result for that series (tests/golden/c4/, one file per series),
+    and every series identical to a single-series call."""
     dev = _dev()
-    from paper_2304_01660_amd import api
+    from paper_2304_01660_amd import api, tuning
     ws = synth.config4()
-    _say("config4 batched", len(ws))
+    gold = {}
+    gdir = os.path.join(os.path.dirname(__file__), "golden", "c4")
+    for b, w in enumerate(ws):
+        path = os.path.join(gdir, f"{b:02d}_{w.name}.json")
+        if os.path.exists(path):
+            gold[b] = json.load(open(path))
+    if len(gold) < len(ws):
+        pytest.skip(f"config-4 goldens incomplete ({len(gold)} of {len(ws)})")
+    opts = tuning.batch_options()
+    _say("config4 batched", len(ws), opts)
     res, st = api.discords_batched([torch.from_numpy(w.T).to(dev) for w in ws],
                                    [w.minL for w in ws], [w.maxL for w in ws], 1,
-                                   return_stats=True)
+                                   return_stats=True, **opts)
     _say("config4 stats", st)
-    rng = np.random.default_rng(404)
+    ties = 0
     for b, w in enumerate(ws):
-        one = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, 1)
+        assert synth.sha256(w.T) == gold[b]["sha256"], b
+        ties += match_rows(w.T, res[b], gold[b])
+        one = api.discords(torch.from_numpy(w.T).to(dev), w.minL, w.maxL, 1, **opts)
         for key in KEYS:
             assert torch.equal(res[b][key], one[key]), (b, w.name, key)
-        nn = res[b]["nn_dist"].cpu().numpy()
-        idx = res[b]["idx"].cpu().numpy()
-        nnj = res[b]["nn_idx"].cpu().numpy()
-        L = w.maxL - w.minL + 1
-        assert np.all(res[b]["len"].cpu().numpy() == np.arange(w.minL, w.maxL + 1))
-        assert np.all(nn > 0) and np.all(nn <= 2 * np.sqrt(np.arange(w.minL, w.maxL + 1)) + 1e-12)
-        if b % 8 == 0:
-            q = int(rng.integers(0, L))
-            m = w.minL + q
-            _say("config4 oracle row", b, w.name, m, idx[q])
-            d, j = oracle.nn_row(w.T, m, int(idx[q]))
-            assert abs(d * d - nn[q] * nn[q]) <= 2 * m * 1e-12 + 2e-9 * d * d, (b, q, d, nn[q])
-            assert j == nnj[q]
-            for i in rng.integers(0, w.n - m + 1, size=4):
-                d, _ = oracle.nn_row(w.T, m, int(i))
-                assert d <= nn[q] * (1 + 1e-9), (b, m, i, d, nn[q])
+    _say("config4 near ties", ties)
 
 
 def test_autotune_returns_valid_options_and_same_discords():

@@ -268,3 +268,36 @@ def test_nonfinite_input_is_rejected():
     with pytest.raises(PalmadError) as ei:
         api.discords(torch.from_numpy(T).to(dev), 10, 12, 1)
     assert ei.value.code == -2
+
+
+def test_fp32_selection_equals_fp64_config2():
+    """The FP32 selection sweep with its guard band against the FP64 sweep
+    over the whole 100k-point search: identical rows and identical
+    range-discord counts at every length (a subsequence wrongly pruned in
+    FP32 would change a count)."""
+    dev = _dev()
+    api = _api()
+    from paper_2304_01660_amd import tuning
+    w = synth.config2()
+    T = torch.from_numpy(w.T).to(dev)
+    opts = tuning.options_for(w.n, w.minL, w.maxL)
+    _say("config2 fp32 vs fp64")
+    a = api.discords(T, w.minL, w.maxL, w.k, **dict(opts, dist_bits=32))
+    b = api.discords(T, w.minL, w.maxL, w.k, **dict(opts, dist_bits=64))
+    for key in ("idx", "len", "nn_dist", "nn_idx", "count"):
+        assert torch.equal(a[key], b[key]), key
+
+
+def test_extreme_spread_contrast_stays_exact():
+    """Windows alternating between a spread of 1 and of 1e-3: the FP32 guard
+    band grows with the spread contrast (far above the default), and the
+    search still matches brute force exactly."""
+    dev = _dev()
+    api = _api()
+    rng = np.random.default_rng(321)
+    t = np.arange(6000)
+    T = np.where((t // 600) % 2 == 0, 1e-3, 1.0) * rng.standard_normal(t.shape[0])
+    T = synth.fp32_canonical(T)
+    _say("spread contrast")
+    out = api.discords(torch.from_numpy(T).to(dev), 32, 34, 3, dist_bits=32)
+    _check_against_profiles(T, out, 32, 34, 3)
