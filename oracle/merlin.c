@@ -32,13 +32,15 @@
  *     tie keeps the smaller neighbour index.
  *
  * Built plainly this file is serial.  Built with -fopenmp (the second
- * library the Python wrapper offers, for the largest workloads), the inner
- * loop over the current candidates of each scanned subsequence in both DRAG
- * phases is split over threads once the candidate list is long.  Every
- * decision in that loop depends only on the pair (scanned subsequence,
- * candidate) and on the candidate's own running nearest-neighbour state, so
- * the scan order of Alg. 2 and every result (indices, distances, neighbour
- * indices, evaluation counts) are the same as the serial build's.
+ * library the Python wrapper offers, for the largest workloads), phase 1's
+ * inner loop over the current candidates of each scanned subsequence is
+ * split over threads once the candidate list is long, and phase 2 scans
+ * each candidate on a thread of its own.  Every decision in either loop
+ * depends only on the pair (scanned subsequence, candidate) and on the
+ * candidate's own running nearest-neighbour state, so every candidate sees
+ * the subsequences in the order of Alg. 2 and every result (indices,
+ * distances, neighbour indices, evaluation counts) is the same as the
+ * serial build's.
  */
 #include <math.h>
 #include <stdint.h>
@@ -252,16 +254,27 @@ static uint64_t phase1_hits_par(const series_m* s, int64_t sidx, const int64_t* 
     return ev;
 }
 
-static uint64_t phase2_step_par(const series_m* s, int64_t sidx, const int64_t* cand, int64_t nc,
-                                int prune, double r2, double* nn2, int64_t* nnj,
-                                unsigned char* hit)
+/*
+ * The whole of phase 2 with the candidates split over threads.  A
+ * candidate's fate in phase 2 depends only on its own scan: it is compared
+ * with the subsequences in increasing order until one of them is closer
+ * than r, and its running nearest neighbour is its own.  Scanning each
+ * candidate to the end (or to its first hit) on its own thread therefore
+ * evaluates exactly the pairs the interleaved scan evaluates, in the same
+ * order per candidate, with the same results.  hit[a] = 1 marks a
+ * candidate dropped by a hit.
+ */
+static uint64_t phase2_par(const series_m* s, const int64_t* cand, int64_t nc, int prune,
+                           double r2, double* nn2, int64_t* nnj, unsigned char* hit)
 {
     uint64_t ev = 0;
-    int64_t chunk = 64;
-#pragma omp parallel for schedule(dynamic) reduction(+ : ev)
-    for (int64_t a0 = 0; a0 < nc; a0 += chunk) {
-        int64_t a1 = a0 + chunk < nc ? a0 + chunk : nc;
-        ev += phase2_step(s, sidx, cand, a0, a1, prune, r2, nn2, nnj, hit);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : ev)
+    for (int64_t a = 0; a < nc; ++a) {
+        hit[a] = 0;
+        for (int64_t sidx = 0; sidx < s->N; ++sidx) {
+            ev += phase2_step(s, sidx, cand, a, a + 1, prune, r2, nn2, nnj, hit);
+            if (hit[a]) break;
+        }
     }
     return ev;
 }
@@ -336,13 +349,17 @@ static int drag_core(const series_m* s, double r, int64_t* out_idx, double* out_
     /* The candidate list stays sorted by index (phase 1 appends in scan
        order and removal keeps relative order), so dead entries can be
        compacted out as the scan proceeds. */
-    for (int64_t sidx = 0; sidx < N; ++sidx) {
 #ifdef _OPENMP
-        if (nc >= PAR_MIN_CANDIDATES)
-            ev += phase2_step_par(s, sidx, cand, nc, prune, r2, nn2, nnj, hit);
-        else
+    if (nc >= 2) {
+        ev += phase2_par(s, cand, nc, prune, r2, nn2, nnj, hit);
+        int64_t w = 0;
+        for (int64_t a = 0; a < nc; ++a)
+            if (!hit[a]) cand[w++] = cand[a];
+        nc = w;
+    } else
 #endif
-            ev += phase2_step(s, sidx, cand, 0, nc, prune, r2, nn2, nnj, hit);
+    for (int64_t sidx = 0; sidx < N; ++sidx) {
+        ev += phase2_step(s, sidx, cand, 0, nc, prune, r2, nn2, nnj, hit);
         int64_t w = 0;
         for (int64_t a = 0; a < nc; ++a)
             if (!hit[a]) cand[w++] = cand[a];

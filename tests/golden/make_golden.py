@@ -6,8 +6,12 @@ stored), and the oracle's MERLIN output.  The values come from the CPU
 oracle in ``oracle/merlin.c`` and nothing else.
 
 Usage:
-    python tests/golden/make_golden.py c1 [c2 c3 c5 ...]
+    python tests/golden/make_golden.py c1 [c2 c3 c5 ...] [--threads T]
     python tests/golden/make_golden.py c4 [--jobs J] [--series 0,5,7]
+
+``--threads T`` runs the OpenMP build of the same oracle source (identical
+results, tested against the serial build) on T threads; the million-point
+workload needs it to finish in hours rather than days.
 
 ``c4`` writes one file per series of the 64-series batch under
 ``tests/golden/c4/`` (the series are independent problems), J series at a
@@ -39,7 +43,7 @@ CONFIGS = {
 C4_DIR = os.path.join(HERE, "c4")
 
 
-def _host():
+def _host(threads=None):
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -49,16 +53,18 @@ def _host():
                     break
     except OSError:
         pass
-    return {"cpu": model or platform.machine(), "threads_used": 1}
+    return {"cpu": model or platform.machine(), "threads_used": threads or 1,
+            "nproc": os.cpu_count()}
 
 
-def record(w):
+def record(w, threads=None):
     t0 = time.time()
-    o = oracle.merlin(w.T, w.minL, w.maxL, w.k)
+    o = oracle.merlin(w.T, w.minL, w.maxL, w.k, threads=threads)
     dt = time.time() - t0
     return {
         "workload": w.name,
-        "source": "oracle/merlin.c oracle_merlin (serial FP64 MERLIN + DRAG)",
+        "source": ("oracle/merlin.c oracle_merlin (FP64 MERLIN + DRAG, "
+                   + (f"OpenMP build, {threads} threads)" if threads else "serial)")),
         "n": w.n, "minL": w.minL, "maxL": w.maxL, "k": w.k,
         "sha256": synth.sha256(w.T),
         "idx": [int(v) for v in o["idx"]],
@@ -69,13 +75,13 @@ def record(w):
         "r": [float(v) for v in o["r"]],
         "evals": int(o["evals"]),
         "oracle_seconds": dt,
-        "oracle_host": _host(),
+        "oracle_host": _host(threads),
     }
 
 
-def write(tag: str) -> str:
+def write(tag: str, threads=None) -> str:
     w = CONFIGS[tag]()
-    rec = record(w)
+    rec = record(w, threads)
     path = os.path.join(HERE, f"{tag}_{w.name}.json")
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -112,7 +118,11 @@ def write_c4(jobs: int, series=None):
 
 if __name__ == "__main__":
     args = sys.argv[1:]
-    jobs, series = 1, None
+    jobs, series, threads = 1, None, None
+    if "--threads" in args:
+        i = args.index("--threads")
+        threads = int(args[i + 1])
+        del args[i:i + 2]
     if "--jobs" in args:
         i = args.index("--jobs")
         jobs = int(args[i + 1])
@@ -125,4 +135,4 @@ if __name__ == "__main__":
         if tag == "c4":
             write_c4(jobs, series)
         else:
-            print(write(tag), flush=True)
+            print(write(tag, threads), flush=True)

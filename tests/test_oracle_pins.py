@@ -340,11 +340,12 @@ def test_r_schedule_follows_alg1_on_bruteforce_values():
 
 
 def test_openmp_build_matches_serial():
-    """The OpenMP build of the oracle (inner candidate loops split over
-    threads, used for the largest stored results) returns exactly what the
-    serial build returns: MERLIN on config 1, and DRAG at a range small
-    enough that hundreds of candidates stay alive, so the threaded branch of
-    both phases runs."""
+    """The OpenMP build of the oracle (phase 1's inner candidate loop split
+    over threads, phase 2 one candidate per thread; used for the largest
+    stored results) returns exactly what the serial build returns,
+    evaluation counts included: MERLIN on config 1, and DRAG at a range
+    small enough that hundreds of candidates stay alive, so the threaded
+    branch of phase 1 runs too."""
     w = synth.config1()
     a = oracle.merlin(w.T, w.minL, w.maxL, w.k)
     b = oracle.merlin(w.T, w.minL, w.maxL, w.k, threads=4)
