@@ -26,10 +26,18 @@
  *     given to the call and before any work queued there later; it returns
  *     once the result is complete (the adaptive r loop reads one counter
  *     every few rounds of range searches).
- *   - Every function returns a palmad_status.  Arguments are validated on
- *     the host before any device work; on error nothing is written to the
- *     outputs and palmad_last_error() describes the problem.  No C++
+ *   - Every function returns a palmad_status and palmad_last_error()
+ *     describes a failure.  Arguments are validated on the host before any
+ *     device work; on an argument error (PALMAD_EINVAL, PALMAD_EWORKSPACE,
+ *     PALMAD_EUNSUPPORTED) or PALMAD_ENONFINITE nothing is written to the
+ *     outputs.  After PALMAD_EDEVICE the outputs are undefined: rows of the
+ *     lengths finished before the failure may have been written.  No C++
  *     exception crosses this interface.
+ *   - The environment variable PALMAD_FAULT injects failures for tests of
+ *     the error paths: "hip" makes a search fail as if its first HIP call
+ *     had failed (PALMAD_EDEVICE, no device work); "converge" allows one
+ *     range search per length, so a search reports a range search that did
+ *     not converge (PALMAD_EDEVICE after device work).
  *   - One context per host thread at a time.  The context caches the
  *     hipGraph of one round of the search for the last workspace and
  *     configuration it saw, and replays it while they stay the same.

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -168,8 +169,28 @@ SweepCfg cfg_of(const Opts& o, const KernelTimer* timer)
     c.q_near = near_rows / 64;
     c.q_far = far_rows / 64;
     c.q_ref = ref_rows / 64;
+    c.max_attempts = MAX_ATTEMPTS;
     c.timer = timer;
     return c;
+}
+
+// Failure injection for error-path tests, from the environment variable
+// PALMAD_FAULT (read at every search):
+//   "hip"       the search fails as if its first HIP call had failed
+//               (PALMAD_EDEVICE before any device work);
+//   "converge"  one range search per length is allowed, so the first
+//               length's opening range (the largest possible distance, which
+//               no subsequence reaches) fails and the search reports a range
+//               search that did not converge (PALMAD_EDEVICE after device
+//               work, with every kernel exiting normally).
+enum Fault { FAULT_NONE = 0, FAULT_HIP, FAULT_CONVERGE };
+Fault fault_site()
+{
+    const char* f = std::getenv("PALMAD_FAULT");
+    if (!f) return FAULT_NONE;
+    if (std::strcmp(f, "hip") == 0) return FAULT_HIP;
+    if (std::strcmp(f, "converge") == 0) return FAULT_CONVERGE;
+    return FAULT_NONE;
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -330,10 +351,10 @@ int prepare(palmad_ctx* ctx, const Batch& bt, const Plan& p)
 std::string graph_key(const Batch& bt, const SweepCfg& c, const Plan& p)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "%p|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%a|", (void*)bt.s, bt.B,
+    snprintf(buf, sizeof buf, "%p|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%a|%d|", (void*)bt.s, bt.B,
              bt.maxL_all, (long long)bt.Nmax_all,
              c.near_cols, c.chunk_cols, c.dist_bits, c.far_grid, c.q_near, c.q_far, c.q_ref,
-             (double)c.guard);
+             (double)c.guard, c.max_attempts);
     std::string k = buf;
     for (int q = 0; q < PFX_KINDS; ++q) k += std::to_string(p.totals[q]) + ",";
     return k;
@@ -428,7 +449,11 @@ int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double
 {
     const auto t0 = std::chrono::steady_clock::now();
     KernelTimer timer = make_timer(ctx, o);
-    const SweepCfg cfg = cfg_of(o, &timer);
+    SweepCfg cfg = cfg_of(o, &timer);
+    const Fault fault = fault_site();
+    if (fault == FAULT_HIP)
+        return fail(ctx, PALMAD_EDEVICE, "injected HIP failure (PALMAD_FAULT=hip)");
+    if (fault == FAULT_CONVERGE) cfg.max_attempts = 1;
     int rc = enter(ctx, stream);
     if (rc) return rc;
     Batch bt;
@@ -439,7 +464,7 @@ int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double
     const bool graphs = !timer.on && !(o.flags & PALMAD_FLAG_NO_GRAPH);
     int64_t max_rounds = 0;
     for (int b = 0; b < p.B; ++b) max_rounds = std::max<int64_t>(max_rounds, p.lay[b].L);
-    max_rounds = max_rounds * MAX_ATTEMPTS + 2;
+    max_rounds = max_rounds * cfg.max_attempts + 2;
     for (int64_t round = 0;;) {
         if (round > max_rounds) return fail(ctx, PALMAD_EDEVICE, "search did not terminate");
         int issued = 0;
@@ -454,7 +479,7 @@ int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double
         if (ctx->pinned[1])
             return fail(ctx, PALMAD_EDEVICE,
                         "%d series: a range search did not converge within %d attempts",
-                        ctx->pinned[1], MAX_ATTEMPTS);
+                        ctx->pinned[1], cfg.max_attempts);
         if (ctx->pinned[0] == 0) break;
     }
     const double secs =

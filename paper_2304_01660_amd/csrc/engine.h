@@ -61,7 +61,7 @@ struct Ctrl {
     int32_t finished;  // 1 once every length is done (or on error)
     int32_t started;
     int32_t new_len;   // 0: same length as last round, 1: update statistics, 2: initialise
-    int32_t error;     // 1: did not converge within MAX_ATTEMPTS
+    int32_t error;     // 1: did not converge within SweepCfg::max_attempts
     int32_t nonfinite; // set when the series holds NaN/Inf
     double flat_eps;   // sigma threshold of a flat window
     double sigmaT;     // population sigma of the whole series
@@ -188,6 +188,7 @@ struct SweepCfg {
     int dist_bits;
     int far_grid;              // workgroups of the queued passes
     int q_near, q_far, q_ref;  // rows per lane of each pass's tiles (2, 4 or 8)
+    int max_attempts;          // range searches allowed per length (MAX_ATTEMPTS)
     const KernelTimer* timer;
 };
 

@@ -240,7 +240,7 @@ __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
     }
 }
 
-__global__ void k_round_prep(SeriesDev* S, int B, float guard, int32_t* rem)
+__global__ void k_round_prep(SeriesDev* S, int B, float guard, int max_attempts, int32_t* rem)
 {
     if (threadIdx.x == 0) {
         rem[0] = 0;
@@ -274,7 +274,7 @@ __global__ void k_round_prep(SeriesDev* S, int B, float guard, int32_t* rem)
         } else {
             c->attempt += 1;
             c->new_len = 0;
-            if (c->attempt >= MAX_ATTEMPTS) {
+            if (c->attempt >= max_attempts) {
                 c->error = 1;
                 c->finished = 1;
                 c->active = 0;
@@ -2191,7 +2191,7 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
 {
     const unsigned int elem = (unsigned int)total[PFX_ELEM];
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(256), 0, st, bt.s, bt.B, cfg.guard,
-                       bt.remaining);
+                       cfg.max_attempts, bt.remaining);
     cfg.timer->begin(4, st);
     hipLaunchKernelGGL(k_length, dim3(elem), dim3(256), 0, st, bt.s, bt.B, bt.pfx[PFX_ELEM]);
     cfg.timer->end(4, st);
