@@ -351,6 +351,31 @@ int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_
 int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
                         void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or any allocating routine: tight serving loops, harnesses that
+ * forbid allocation).  Same search and results as palmad_discords() with
+ * the same options, but the workspace is a static device array of
+ * PALMAD_STATIC_WORKSPACE_BYTES bytes held by each GPU the library runs on
+ * until the process ends (its address is taken once per device by
+ * palmad_create()).  The call allocates no device memory and launches every
+ * kernel directly (no graph is instantiated).
+ *
+ *   T ... count, stats, stream  as palmad_discords().
+ * Returns PALMAD_EWORKSPACE when palmad_workspace_size() for these
+ * arguments exceeds PALMAD_STATIC_WORKSPACE_BYTES (about 3.5e5 points at
+ * m = 64..128, k = 3).  Every call on one GPU uses that GPU's array, whose
+ * contents persist from the last call (the search initialises everything it
+ * reads).  Calls from threads of one process are serialised by the library;
+ * calls from different processes use different copies.  A call returns only
+ * once its device work is complete.
+ */
+#define PALMAD_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+int palmad_discords_static(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL,
+                           int32_t maxL, int32_t k, const palmad_options* opts, int64_t* idx,
+                           int32_t* len, double* nn_dist, int64_t* nn_idx, int32_t* count,
+                           palmad_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,8 @@ class TuneReport(ctypes.Structure):
     ]
 
 
+# PALMAD_STATIC_WORKSPACE_BYTES: the static workspace of palmad_discords_static
+STATIC_WORKSPACE_BYTES = 32 << 20
 FLAG_TIME_KERNELS = 1
 FLAG_NO_GRAPH = 2
 KERNEL_CLASSES = ("select_near", "select_far", "refine", "polish")
@@ -123,6 +125,9 @@ SIGNATURES = {
                                                _vp, _vp, _vp, _vp]),
     "palmad_window_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                            _vp, _vp]),
+    "palmad_discords_static": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32,
+                                              ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp,
+                                              ctypes.POINTER(Stats), _vp]),
     "palmad_backward_workspace_size": (ctypes.c_int, [_i64, _i64, _i32,
                                                       ctypes.POINTER(ctypes.c_size_t)]),
     "palmad_discords_backward": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, _vp,

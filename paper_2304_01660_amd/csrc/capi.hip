@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,11 +36,24 @@ struct palmad_ctx {
     hipGraph_t graph;            // cached round graph
     hipGraphExec_t graph_exec;
     std::string graph_key;
+    void* scratch;               // device address of this device's static workspace
 };
+
+// Static workspace of palmad_discords_static(): one copy per GPU, held
+// until the process ends.  In host code this name is only a stand-in for
+// the symbol; its device address (a different one on every GPU) comes from
+// hipGetSymbolAddress with that device current, taken once per device by
+// palmad_create() and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[PALMAD_STATIC_WORKSPACE_BYTES];
 
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;                // guards g_scratch
+void* g_scratch[SCRATCH_DEVICES];       // device address of each GPU's scratch (or null)
+std::mutex g_scratch_use[SCRATCH_DEVICES];  // one static-workspace call per GPU at a time
 
 int fail(palmad_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int fail(palmad_ctx* ctx, int code, const char* fmt, ...)
@@ -614,6 +628,23 @@ int palmad_create(palmad_ctx** out, int device)
     for (int k = 0; k < KCLASSES; ++k)
         for (int q = 0; q < 2; ++q)
             if (hipEventCreate(&ctx->ev[k][q]) != hipSuccess) ctx->have_events = false;
+    // the static workspace's address on this device (once per device; the
+    // device is current here)
+    ctx->scratch = nullptr;
+    if (device < SCRATCH_DEVICES) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            void* ptr = nullptr;
+            const hipError_t es = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (es != hipSuccess || !ptr) {
+                palmad_destroy(ctx);
+                return fail(nullptr, PALMAD_EDEVICE, "static workspace address on device %d: %s",
+                            device, hipGetErrorString(es));
+            }
+            g_scratch[device] = ptr;
+        }
+        ctx->scratch = g_scratch[device];
+    }
     *out = ctx;
     return PALMAD_OK;
 }
@@ -668,6 +699,39 @@ int palmad_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, i
     if (rc) return rc;
     const Outputs out = {idx, len, nn_dist, nn_idx, count};
     return search(ctx, p, o, workspace, &T, &out, stats, stream);
+}
+
+int palmad_discords_static(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL,
+                           int32_t maxL, int32_t k, const palmad_options* opts, int64_t* idx,
+                           int32_t* len, double* nn_dist, int64_t* nn_idx, int32_t* count,
+                           palmad_stats* stats, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!T || !idx || !len || !nn_dist || !nn_idx || !count)
+        return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    int rc = validate(ctx, n, minL, maxL, k);
+    if (rc) return rc;
+    Opts o;
+    rc = read_opts(ctx, opts, &o);
+    if (rc) return rc;
+    Plan p;
+    make_plan(1, &n, &minL, &maxL, k, cfg_of(o, nullptr), &p);
+    if (p.total > (size_t)PALMAD_STATIC_WORKSPACE_BYTES)
+        return fail(ctx, PALMAD_EWORKSPACE,
+                    "this search needs %zu bytes of workspace; the static workspace holds %zu "
+                    "(use palmad_discords with a caller workspace)",
+                    p.total, (size_t)PALMAD_STATIC_WORKSPACE_BYTES);
+    if (!ctx->scratch)
+        return fail(ctx, PALMAD_EUNSUPPORTED, "no static workspace on device %d", ctx->device);
+    // graph instantiation may allocate: every kernel is launched directly
+    o.flags |= PALMAD_FLAG_NO_GRAPH;
+    const Outputs out = {idx, len, nn_dist, nn_idx, count};
+    // search() returns after its device work completed, so holding the
+    // device's lock for the call keeps calls from this process apart
+    std::lock_guard<std::mutex> lk(g_scratch_use[ctx->device]);
+    rc = search(ctx, p, o, ctx->scratch, &T, &out, stats, stream);
+    if (rc) (void)hipStreamSynchronize(ctx->work);  // an error may leave work queued
+    return rc;
 }
 
 int palmad_discord_heatmap(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL,
