@@ -72,7 +72,9 @@ typedef struct {
                               threshold by more than this.  <= 0 = 1e-4. */
     int32_t near_cols;     /* columns scanned by the first selection pass of a row
                               tile (in chunks of chunk_cols run concurrently) before
-                              the remaining columns go to the queued pass; 0 = 2048. */
+                              the remaining columns go to the queued pass; 0 = 2048.
+                              Capped so that the longest series has at most 65536
+                              (tile, chunk) items in the first pass. */
     int32_t chunk_cols;    /* columns per work item of the sweeps; 0 = 1024. */
     uint32_t flags;        /* PALMAD_FLAG_* bits */
     int32_t rows_near;     /* row-tile height of the first selection pass: 128, 256 or
@@ -141,7 +143,7 @@ void palmad_destroy(palmad_ctx* ctx);
  * context).  Returns PALMAD_EINVAL for arguments palmad_discords() would
  * reject: minL < 3, maxL < minL, n < 3*maxL - 1 (so that every subsequence
  * has a non-self match), k < 1 or k > n - maxL + 1; PALMAD_EUNSUPPORTED for
- * k > 64 or maxL > 3000.
+ * k > 64 or maxL > 2800.
  */
 int palmad_workspace_size(int64_t n, int32_t minL, int32_t maxL, int32_t k,
                           const palmad_options* opts, size_t* bytes);

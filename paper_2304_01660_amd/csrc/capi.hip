@@ -125,9 +125,10 @@ int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
     return PALMAD_OK;
 }
 
-// Largest length whose LDS staging (two centred windows + padding, FP64)
-// fits a 64 KiB workgroup allocation.
-constexpr int32_t MAXL_LIMIT = 3000;
+// Largest length whose sweep staging (a padded centred window, a skewed
+// series stretch of 512 + m + 16 values, a batch of FP64 step records and
+// the refinement's per-row values) fits a 64 KiB workgroup allocation.
+constexpr int32_t MAXL_LIMIT = 2800;
 constexpr int32_t B_LIMIT = 65535;
 
 int validate(palmad_ctx* ctx, int64_t n, int32_t minL, int32_t maxL, int32_t k)
@@ -220,10 +221,20 @@ struct Plan {
     std::vector<int64_t> pfx;  // [PFX_KINDS][B+1]
     int32_t maxL_all;
     int64_t Nmax_all;
+    int near_cols;  // first-pass width actually used (see NEAR_ITEMS)
 };
 
+// The first selection pass launches one workgroup per (row tile, chunk) of
+// every series, most of which find their tile dead and exit; past a few
+// tens of thousands of them per series their dispatch costs more than the
+// queued split pass, which draws only live tiles' chunks.  The first-pass
+// width is therefore capped so that the largest series has at most
+// NEAR_ITEMS of them (at least one chunk per tile); the remaining columns
+// go to the split pass.
+constexpr int64_t NEAR_ITEMS = 65536;
+
 void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL, int32_t k,
-               const SweepCfg& cfg, Plan* p)
+               const SweepCfg& cfg_in, Plan* p)
 {
     p->B = B;
     p->lay.resize(B);
@@ -239,12 +250,22 @@ void make_plan(int B, const int64_t* n, const int32_t* minL, const int32_t* maxL
         make_layout(n[b], minL[b], maxL[b], k, &p->lay[b]);
         p->base[b] = o;
         o = al256(o + p->lay[b].total);
+        p->maxL_all = std::max(p->maxL_all, maxL[b]);
+        p->Nmax_all = std::max(p->Nmax_all, p->lay[b].Nmax);
+    }
+    SweepCfg cfg = cfg_in;
+    {
+        const int64_t rows = 64 * (int64_t)cfg.q_near;
+        const int64_t tiles = (p->Nmax_all + rows - 1) / rows;
+        const int64_t chunks = std::max<int64_t>(1, NEAR_ITEMS / std::max<int64_t>(1, tiles));
+        cfg.near_cols = (int)std::min<int64_t>(cfg.near_cols, chunks * cfg.chunk_cols);
+    }
+    p->near_cols = cfg.near_cols;
+    for (int b = 0; b < B; ++b) {
         int64_t blk[PFX_KINDS];
         series_blocks(p->lay[b], cfg, blk);
         for (int q = 0; q < PFX_KINDS; ++q)
             p->pfx[(size_t)q * (B + 1) + b + 1] = p->pfx[(size_t)q * (B + 1) + b] + blk[q];
-        p->maxL_all = std::max(p->maxL_all, maxL[b]);
-        p->Nmax_all = std::max(p->Nmax_all, p->lay[b].Nmax);
     }
     for (int q = 0; q < PFX_KINDS; ++q) p->totals[q] = p->pfx[(size_t)q * (B + 1) + B];
     p->total = o;
@@ -271,14 +292,17 @@ struct Outputs {
 };
 
 // Write the descriptors and prefix tables into the workspace (one upload).
+// n_now (optional): the current length of each series when it is shorter
+// than the length its layout was planned for (a streaming series).
 int upload(palmad_ctx* ctx, const Plan& p, void* ws, const double* const* Tin, const Outputs* outs,
-           Batch* bt)
+           Batch* bt, const int64_t* n_now = nullptr)
 {
     std::vector<char> blob(p.off_rem, 0);
     SeriesDev* d = (SeriesDev*)blob.data();
     for (int b = 0; b < p.B; ++b) {
         SeriesDev s = carve((char*)ws + p.base[b], p.lay[b]);
-        s.Tin = Tin[b];
+        s.Tin = Tin ? Tin[b] : nullptr;
+        if (n_now) s.n = n_now[b];
         if (outs) {
             s.idx = outs[b].idx;
             s.len = outs[b].len;
@@ -468,6 +492,7 @@ int search(palmad_ctx* ctx, const Plan& p, const Opts& o, void* ws, const double
     if (fault == FAULT_HIP)
         return fail(ctx, PALMAD_EDEVICE, "injected HIP failure (PALMAD_FAULT=hip)");
     if (fault == FAULT_CONVERGE) cfg.max_attempts = 1;
+    cfg.near_cols = p.near_cols;
     int rc = enter(ctx, stream);
     if (rc) return rc;
     Batch bt;
@@ -850,9 +875,10 @@ int palmad_range_discords(palmad_ctx* ctx, const double* T, int64_t n, int32_t m
     rc = read_opts(ctx, opts, &o);
     if (rc) return rc;
     KernelTimer timer = make_timer(ctx, o);
-    const SweepCfg cfg = cfg_of(o, &timer);
+    SweepCfg cfg = cfg_of(o, &timer);
     Plan p;
     make_plan(1, &n, &m, &m, 1, cfg, &p);
+    cfg.near_cols = p.near_cols;
     rc = check_ws(ctx, workspace, ws_bytes, p.total);
     if (rc) return rc;
     rc = enter(ctx, stream);
@@ -1033,22 +1059,29 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
         {&cur.chunk_cols, chunk_v, 4}, {&cur.near_cols, near_v, 4},  {&cur.rows_near, rows_v, 3},
         {&cur.rows_far, rows_v, 3},    {&cur.rows_refine, rows_v, 3}, {&cur.far_grid, grid_v, 5},
     };
-    for (const Axis& ax : axes) {
-        const int keep = *ax.field;
-        int best_v = keep;
-        for (int i = 0; i < ax.count; ++i) {
-            if (ax.vals[i] == keep) continue;
-            *ax.field = ax.vals[i];
-            double t = 0.0;
-            rc = time_probe(ctx, pr, k, cur, workspace, tin, outs, reps, stream, &t);
-            if (rc) return rc;
-            ++evaluated;
-            if (t < t_best) {
-                t_best = t;
-                best_v = ax.vals[i];
+    // coordinate search, two passes over the axes (the best chunk length and
+    // first-pass width depend on the tile heights chosen after them)
+    for (int pass = 0; pass < 2; ++pass) {
+        bool moved = false;
+        for (const Axis& ax : axes) {
+            const int keep = *ax.field;
+            int best_v = keep;
+            for (int i = 0; i < ax.count; ++i) {
+                if (ax.vals[i] == keep) continue;
+                *ax.field = ax.vals[i];
+                double t = 0.0;
+                rc = time_probe(ctx, pr, k, cur, workspace, tin, outs, reps, stream, &t);
+                if (rc) return rc;
+                ++evaluated;
+                if (t < t_best) {
+                    t_best = t;
+                    best_v = ax.vals[i];
+                }
             }
+            *ax.field = best_v;
+            moved = moved || best_v != keep;
         }
-        *ax.field = best_v;
+        if (!moved) break;
     }
     palmad_options r = {};
     r.dist_bits = cur.dist_bits;
@@ -1069,5 +1102,7 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
     }
     return PALMAD_OK;
 }
+
+
 
 }  // extern "C"

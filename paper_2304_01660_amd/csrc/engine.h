@@ -77,9 +77,6 @@ struct Ctrl {
     uint32_t live_ref;     // live subsequences entering refinement this round
     uint32_t nsurv;
     uint32_t ncand;
-    // work-queue heads (items: chunk-major)
-    alignas(128) unsigned long long ctr_sel;
-    alignas(128) unsigned long long ctr_ref;
     // counters accumulated over the call
     alignas(128) unsigned long long rounds, survivors;
     unsigned long long rows_near, rows_far;  // live rows entering the split / refinement passes

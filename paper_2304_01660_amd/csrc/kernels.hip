@@ -43,7 +43,6 @@ namespace palmad {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-constexpr int PF_T = 4;  // 64-value groups of a block's T segment prefetched into registers
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l <- lane l-1
 constexpr int DPP_WAVE_ROL1 = 0x134;  // lane l <- lane l+1 (63 <- 0)
 
@@ -229,7 +228,6 @@ __device__ void begin_range(const SeriesDev& s, Ctrl* c, float guard)
     set_sel_thresholds(c, guard);
     c->nlive_sel = c->maxc_sel = 0;
     c->nlive_ref = c->maxc_ref = 0;
-    c->ctr_sel = c->ctr_ref = 0ull;
     c->nsurv = 0;
     c->ncand = 0;
     c->live_ref = 0;
@@ -511,229 +509,192 @@ __device__ __forceinline__ void lds_fill(double* dst, const double* __restrict__
     }
 }
 
-// LDS index of value p of the tile's row windows while the first column is
-// computed: one pad value after every Q, so that lanes reading values Q apart
-// (each lane holds Q consecutive rows) hit distinct banks.
-template <int Q>
-__device__ __forceinline__ int skw(int p)
-{
-    return p + p / Q;
-}
+// ----- exact values from the FP64 matrix cores -----
+// A sweep needs exact FP64 centred dot products in two places: the first
+// column of a work item (one per row of the tile) and the top row of the
+// tile at every later column (the boundary that feeds the recurrence).
+// Both are correlations of one short centred window v (m values) with a
+// stretch of the series w:
+//     D(p) = sum_k v[k] w[p + k],   p = 0 .. 255,
+// which is one 16 x 16 tile of V_MFMA_F64_16X16X4F64 with the Toeplitz
+// operand A[r][k] = v[k - r] and the Hankel operand B[k][c] = w[16 c + k]:
+// D[r][c] = D(16 c + r).  Lane l supplies A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16] and receives D[l / 16 + 4 q][l % 16], q < 4, i.e.
+// D(p) for p = 16 (l % 16) + l / 16 + 4 q.  Two LDS reads per matrix
+// instruction (1024 multiply-adds) replace the two reads per multiply-add of
+// a vector loop, which left the sweeps bound by LDS bandwidth.
+typedef double pm_acc_t __attribute__((ext_vector_type(4)));
+constexpr int HK_PAD = 16;   // zeros before v (k - r >= -15)
+constexpr int BCOLS = 256;   // columns per boundary batch (one tile)
+// w is staged skewed (value p at p + p / 16), so that the 16 lanes reading
+// w[16 c + k] for c = 0..15 hit distinct LDS banks.
+__host__ __device__ constexpr int hk_skew(int p) { return p + (p >> 4); }
+// k < 4 hk_steps(m) covers every k - r < m for r < 16
+__host__ __device__ constexpr int hk_steps(int m) { return (m + 15 + 3) >> 2; }
+// v with HK_PAD zeros before and zeros after: HK_PAD + 4 hk_steps(m) values
+__host__ __device__ constexpr int hk_vp_doubles(int m) { return (HK_PAD + 4 * hk_steps(m) + 3) & ~3; }
 
-// lds_fill into the skewed layout.
-template <int Q>
-__device__ __forceinline__ void lds_fill_skew(double* dst, const double* __restrict__ src, int count)
+__device__ __forceinline__ int hk_offset(int q)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int base = 0; base < count; base += nt * 8) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = base + tid + nt * u;
-            v[u] = t < count ? src[t] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = base + tid + nt * u;
-            if (t < count) dst[skw<Q>(t)] = v[u];
-        }
-    }
-}
-
-// Start of a sweep work item (one wavefront, row tile of R = 64 Q rows from
-// i0, first column jbeg):
-//  * acc[q] = C(rbase + q, jbeg), rbase = i0 + Q lane: centred dot products
-//    sum_k t_{i+k} y_k - mu_i Sy with y the centred window of column jbeg
-//    (staged in xs).  The rows' windows are staged in sk (skewed); each lane
-//    walks its Q consecutive rows along k with a ring of P row values, so
-//    that one LDS read per step serves all Q rows and is issued P - Q + 1
-//    steps before its first use;
-//  * xs then holds the centred window of the tile's top row zero padded by
-//    64, with sum Sx (zero up to rounding), for the top-boundary values, and
-//    sk is free again.
-// xs must hold m + 64 values, sk sweep_skew_doubles(m, R).
-template <int Q>
-__host__ __device__ constexpr int start_ring()
-{
-    return Q <= 4 ? 2 * Q : Q;  // the tallest tiles have no registers to spare
-}
-template <int Q>
-__host__ __device__ constexpr int start_steps(int m)
-{
-    return ((m + start_ring<Q>() - 1) / start_ring<Q>()) * start_ring<Q>();
-}
-template <int Q>
-__host__ __device__ constexpr int start_rows(int m)
-{
-    return 64 * Q + start_steps<Q>(m) + start_ring<Q>();
-}
-
-template <int Q>
-__device__ void item_start(const double* __restrict__ T, const double* __restrict__ mu, int32_t m,
-                           int64_t i0, int64_t jbeg, double* xs, double* sk, double& Sx,
-                           double& Sy, double (&acc)[Q])
-{
-    constexpr int P = start_ring<Q>();  // ring of row values
     const int lane = threadIdx.x;
-    const int mp = start_steps<Q>(m);
-    const double muj = mu[jbeg], mui0 = mu[i0];
-    double mr[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) mr[q] = mu[i0 + Q * lane + q];
-    // one burst of loads: the column window (xs, zero from m on) first, it is
-    // needed first, then the rows' windows
-    {
+    return 16 * (lane & 15) + (lane >> 4) + 4 * q;
+}
+
+// D(p) for p < 256 (see above): vp = v after HK_PAD zeros, zero beyond m;
+// w = skewed LDS stretch starting at value wbase, at least wbase + 255 + m
+// + 16 values.  One accumulator (the matrix core chains dependent
+// accumulations), so the sweep keeps its registers.
+__device__ __forceinline__ pm_acc_t hankel16(const double* vp, const double* w, int wbase, int m)
+{
+    const int lane = threadIdx.x;
+    const int ca = lane & 15, ka = lane >> 4;
+    const int K4 = hk_steps(m);
+    const double* va = vp + HK_PAD + ka - ca;
+    const int wb = wbase + 16 * ca + ka;
+    pm_acc_t d = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < K4; ++s)
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(va[4 * s], w[hk_skew(wb + 4 * s)], d, 0, 0, 0);
+    return d;
+}
+
+// Copy count doubles from src into the skewed LDS stretch w (the whole
+// wave: four loads in flight per lane before their stores).
+__device__ __forceinline__ void stage_skewed(double* w, const double* __restrict__ src, int count)
+{
+    const int lane = threadIdx.x;
+    for (int base = 0; base < count; base += 64 * 4) {
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int t = lane + 64 * u;
-            v[u] = t < m ? T[jbeg + t] : 0.0;
+            const int t = base + lane + 64 * u;
+            v[u] = t < count ? src[t] : 0.0;
         }
-        lds_fill_skew<Q>(sk, T + i0, start_rows<Q>(m));
-        for (int t = lane + 256; t < m + 64; t += 64) xs[t] = t < m ? T[jbeg + t] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int t = lane + 64 * u;
-            if (t < m + 64) xs[t] = v[u];
+            const int t = base + lane + 64 * u;
+            if (t < count) w[hk_skew(t)] = v[u];
         }
     }
-    __syncthreads();
-    double sy = 0.0;
-    for (int k = lane; k < m; k += 64) {
-        const double v = xs[k] - muj;
-        xs[k] = v;
-        sy += v;
-    }
-    Sy = wave_sum(sy);
-    __syncthreads();
-    // ring slot (k + q) mod P holds row value Q lane + k + q at step k; the
-    // slot row 0 used last is refilled P values ahead
-    const int base = Q * lane;
-    double st[Q], r[P];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) st[q] = 0.0;
-#pragma unroll
-    for (int u = 0; u < P; ++u) r[u] = sk[skw<Q>(base + u)];
-    for (int k0 = 0; k0 < mp; k0 += P) {
-#pragma unroll
-        for (int u = 0; u < P; ++u) {
-            const double y = xs[k0 + u];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) st[q] = fma(r[(u + q) % P], y, st[q]);
-            r[u] = sk[skw<Q>(base + k0 + u + P)];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = st[q] - mr[q] * Sy;
-    __syncthreads();
-    double sx = 0.0;
-    for (int k = lane; k < m + 64; k += 64) {
-        const double v = k < m ? sk[skw<Q>(k)] - mui0 : 0.0;
-        xs[k] = v;
-        sx += v;
-    }
-    Sx = wave_sum(sx);
-    __syncthreads();
 }
 
-// Column helpers of one step, staged in LDS per block of 64 columns.
+// Column helpers of one step, staged in LDS per batch of BCOLS columns.
 template <typename F>
 struct alignas(4 * sizeof(F)) H4 {
     F df, dg, inv;  // df[j-1], dg[j-1], 1/(sqrt(m) sigma_j)
     F B;            // C(i0, j): exact value of the tile's top row at column j
 };
 
-// LDS of a sweep work item with R = 64 Q row tiles, in doubles:
-// xs[m + 68] | region, where region holds the tile's skewed row windows
-// while the first column is computed (sweep_skew_doubles) and then, during
-// the sweep, win[max(m + 128, 64 PF_T, R)] | hs[256] | rowv[R] (refinement
-// only: per-row constants read once per block, kept out of registers).  xs
-// holds the first column's window, then the top row's centred window; win
-// holds the T segment of the current block.
-__host__ __device__ constexpr int sweep_xs_doubles(int m) { return (m + 68 + 3) & ~3; }
-__host__ __device__ constexpr int sweep_skew_doubles(int m, int R)
+// LDS of a sweep work item with R-row tiles, in doubles:
+//   xp   [hk_vp_doubles(m)]  the first column's centred window, then the
+//                            tile's top-row centred window (padded for the
+//                            Toeplitz operand)
+//   ws   [sweep_ws_doubles]  skewed series stretch: the rows' windows while
+//                            the first column is computed, then each batch's
+//                            columns
+//   hs   [BCOLS records]     per-step helpers and boundary values of a batch
+//                            (the first column's R row values before that)
+//   rowv [R]                 refinement only: per-row 1/(sqrt(m) sigma_i)
+__host__ __device__ constexpr int sweep_ws_count(int m, int R) { return (R > BCOLS ? R : BCOLS) + m + 16; }
+__host__ __device__ constexpr int sweep_ws_doubles(int m, int R)
 {
-    return R == 128 ? start_rows<2>(m) + start_rows<2>(m) / 2 + 4
-         : R == 256 ? start_rows<4>(m) + start_rows<4>(m) / 4 + 4
-                    : start_rows<8>(m) + start_rows<8>(m) / 8 + 4;
+    return (hk_skew(sweep_ws_count(m, R) - 1) + 1 + 3) & ~3;
 }
-__host__ __device__ constexpr int sweep_win_doubles(int m, int R)
+__host__ __device__ constexpr int sweep_hs_offset(int m, int R) { return hk_vp_doubles(m) + sweep_ws_doubles(m, R); }
+__host__ __device__ constexpr int sweep_hs_doubles(int fbytes) { return BCOLS * 4 * fbytes / 8; }
+__host__ __device__ constexpr int sweep_rowv_offset(int m, int R, int fbytes)
 {
-    return (m + 128 > 64 * PF_T) ? (m + 128 > R ? m + 128 : R) : (64 * PF_T > R ? 64 * PF_T : R);
+    return sweep_hs_offset(m, R) + sweep_hs_doubles(fbytes);
 }
-__host__ __device__ constexpr int sweep_hs_offset(int m, int R)
+__host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, int fbytes, bool rowv)
 {
-    return (sweep_xs_doubles(m) + sweep_win_doubles(m, R) + 3) & ~3;
-}
-__host__ __device__ constexpr int sweep_rowv_offset(int m, int R) { return sweep_hs_offset(m, R) + 256; }
-__host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, bool rowv)
-{
-    return (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0)) >
-                   (size_t)(sweep_xs_doubles(m) + sweep_skew_doubles(m, R))
-               ? (size_t)(sweep_rowv_offset(m, R) + (rowv ? R : 0))
-               : (size_t)(sweep_xs_doubles(m) + sweep_skew_doubles(m, R));
+    return (size_t)(sweep_rowv_offset(m, R, fbytes) + (rowv ? R : 0));
 }
 
-// Staging of one block of 64 columns, software-pipelined: prefetch() issues
-// the global loads of a block into registers (the T segment up to
-// 64 * PF_T values, the column helpers, mu_j) and returns at once, so they
-// travel while the previous block is swept; commit() then writes them to
-// LDS (loading any longer remainder of the T segment directly), and lane l
-// computes the exact top-boundary value B(j0 + l) = C(i0, j0 + l) from LDS.
-// hs[s] then holds everything step s needs.
-template <typename F>
-struct Prefetch {
-    double muj;
-    F df, dg, inv;
-    double tw[PF_T];
-};
-
-template <typename F>
-__device__ __forceinline__ void prefetch(Prefetch<F>& p, const double* __restrict__ T,
-                                         const double* __restrict__ mu, const F* __restrict__ df,
-                                         const F* __restrict__ dg, const F* __restrict__ inv,
-                                         int64_t j0)
+// Start of a sweep work item (one wavefront, row tile of R = 64 Q rows from
+// i0, first column jbeg): acc[q] = C(rbase + q, jbeg), rbase = i0 + Q lane,
+// the centred dot products sum_k t_{i+k} y_k - mu_i Sy with y the centred
+// window of column jbeg, from R / 256 Hankel tiles (the rows' values pass
+// through the hs region); then xp holds the tile's top-row centred window
+// x with sum Sx (zero up to rounding) for the boundary values.
+template <int Q>
+__device__ void item_start(const double* __restrict__ T, const double* __restrict__ mu, int32_t m,
+                           int64_t i0, int64_t jbeg, double* xp, double* ws, double* rowc,
+                           double& Sx, double& Sy, double (&acc)[Q])
 {
+    constexpr int R = 64 * Q;
     const int lane = threadIdx.x;
-    p.muj = mu[j0 + lane];
-    p.df = df[j0 + lane - 1];
-    p.dg = dg[j0 + lane - 1];
-    p.inv = inv[j0 + lane];
+    const int nvp = hk_vp_doubles(m);
+    const double muj = mu[jbeg], mui0 = mu[i0];
+    double mr[Q];
 #pragma unroll
-    for (int q = 0; q < PF_T; ++q) p.tw[q] = T[j0 + lane + 64 * q];
-}
-
-template <typename F>
-__device__ __forceinline__ void commit(const Prefetch<F>& p, const double* __restrict__ T,
-                                       int32_t m, int64_t j0, const double* xs, double Sx,
-                                       double* win, H4<F>* hs)
-{
-    const int lane = threadIdx.x;
-    __syncthreads();  // the previous block is done with win and hs
-#pragma unroll
-    for (int q = 0; q < PF_T; ++q) win[lane + 64 * q] = p.tw[q];
-    for (int t = lane + 64 * PF_T; t < m + 72; t += 64) win[t] = T[j0 + t];
-    __syncthreads();
-    // B: four independent partial sums, each group of eight LDS reads issued
-    // before its FMAs (xs is zero beyond m, win holds m + 72 values)
-    const double* tw = win + lane;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < m; k += 4) {
-        double xv[4], tv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            xv[u] = xs[k + u];
-            tv[u] = tw[k + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = fma(xv[u], tv[u], acc[u]);
+    for (int q = 0; q < Q; ++q) mr[q] = mu[i0 + Q * lane + q];
+    // the column window (xp, zero padded) and the rows' stretch (ws)
+    for (int t = lane; t < nvp; t += 64) {
+        const int k = t - HK_PAD;
+        xp[t] = (k >= 0 && k < m) ? T[jbeg + k] : 0.0;
     }
-    H4<F> h;
-    h.df = p.df;
-    h.dg = p.dg;
-    h.inv = p.inv;
-    h.B = (F)(((acc[0] + acc[1]) + (acc[2] + acc[3])) - p.muj * Sx);
-    hs[lane] = h;
+    stage_skewed(ws, T + i0, sweep_ws_count(m, R));  // (tiles of 128 rows read 256 rows' worth)
+    __syncthreads();
+    double sy = 0.0;
+    for (int k = lane; k < m; k += 64) {
+        const double v = xp[HK_PAD + k] - muj;
+        xp[HK_PAD + k] = v;
+        sy += v;
+    }
+    Sy = wave_sum(sy);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < (R + 255) / 256; ++h) {
+        const pm_acc_t D = hankel16(xp, ws, 256 * h, m);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = 256 * h + hk_offset(q);
+            if (p < R) rowc[p] = D[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = rowc[Q * lane + q] - mr[q] * Sy;
+    // the top row's centred window
+    double sx = 0.0;
+    for (int k = lane; k < m; k += 64) {
+        const double v = ws[hk_skew(k)] - mui0;
+        xp[HK_PAD + k] = v;
+        sx += v;
+    }
+    Sx = wave_sum(sx);
+    __syncthreads();
+}
+
+// One batch of up to BCOLS columns from j0: the series stretch t[j0 ..
+// j0 + BCOLS + m + 16) staged skewed, then hs[p] = {df[j0+p-1], dg[j0+p-1],
+// inv[j0+p], B(j0+p)} with the exact top-row values B(j) = sum_k x_k t_{j+k}
+// - mu_j Sx from one Hankel tile.  Reads stay inside the padded buffers
+// (their padding exceeds one 512-row tile beyond the last subsequence).
+template <typename F>
+__device__ void stage_batch(const double* __restrict__ T, const double* __restrict__ mu,
+                            const F* __restrict__ df, const F* __restrict__ dg,
+                            const F* __restrict__ inv, int32_t m, int64_t j0, const double* xp,
+                            double Sx, double* ws, H4<F>* hs)
+{
+    const int lane = threadIdx.x;
+    __syncthreads();  // the previous batch is consumed
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + lane + 64 * u;
+        H4<F>& h = hs[lane + 64 * u];
+        h.df = df[j - 1];
+        h.dg = dg[j - 1];
+        h.inv = inv[j];
+    }
+    stage_skewed(ws, T + j0, BCOLS + m + 16);
+    __syncthreads();
+    const pm_acc_t D = hankel16(xp, ws, 0, m);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int p = hk_offset(q);
+        hs[p].B = (F)(D[q] - mu[j0 + p] * Sx);
+    }
     __syncthreads();
 }
 
@@ -978,14 +939,14 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
         for (int q = 0; q < Q; ++q) all &= dm[q];
         if (all == ~0ull) return;
     }
-    double* xs = lds;
-    double* ys = lds + sweep_xs_doubles(m);  // win; the skewed rows before the sweep
+    double* xp = lds;
+    double* ws = lds + hk_vp_doubles(m);
     H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     F C[Q];
     {
         double acc[Q];
-        item_start<Q>(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy, acc);
+        item_start<Q>(A.T, A.mu, m, i0, jbeg, xp, ws, (double*)hs, Sx, Sy, acc);
 #pragma unroll
         for (int q = 0; q < Q; ++q) C[q] = (F)acc[q];
     }
@@ -1023,29 +984,32 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     bool go = sync_rows<Q>(A.alive, rbase, dm);
     uint32_t nblk = 0;
     int64_t j = jbeg + 1;
-    Prefetch<F> pf;
-    if (go && j < jend) prefetch<F>(pf, A.T, A.mu, A.df, A.dg, A.inv, j);
     while (go && j < jend) {
-        const int nst = (int)std::min<int64_t>(64, jend - j);
-        commit<F>(pf, A.T, m, j, xs, Sx, ys, hs);
-        const int64_t jn = j + nst;
-        if (jn < jend) prefetch<F>(pf, A.T, A.mu, A.df, A.dg, A.inv, jn);
-        const unsigned long long word = load_word(&A.alive[rbase >> 6]);
-        unsigned long long colbits = 0ull;
-        const bool full = (j - (i0 + R - 1)) >= m;
-        if (Q <= 4 && full && nst == 64)  // taller tiles: the general path keeps fewer registers
-            sel_block_full<F, Q>(C, a, b, nth, rm, hs, colbits);
-        else if (full)
-            sel_block<F, Q, false>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
-        else
-            sel_block<F, Q, true>(A, j, nst, C, a, b, nth, rm, ri, hs, colbits);
-        kill_columns(A.alive, j, colbits);
+        // a batch of up to BCOLS columns (one Hankel tile of boundary
+        // values), swept in blocks of 64 with the bitmap synchronised after
+        // each
+        stage_batch<F>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
+        const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+        for (int sb = 0; go && j < jb_end; ++sb) {
+            const int nst = (int)std::min<int64_t>(64, jb_end - j);
+            const H4<F>* hb = hs + 64 * sb;
+            const unsigned long long word = load_word(&A.alive[rbase >> 6]);
+            unsigned long long colbits = 0ull;
+            const bool full = (j - (i0 + R - 1)) >= m;
+            if (Q <= 4 && full && nst == 64)  // taller tiles: the general path keeps fewer registers
+                sel_block_full<F, Q>(C, a, b, nth, rm, hb, colbits);
+            else if (full)
+                sel_block<F, Q, false>(A, j, nst, C, a, b, nth, rm, ri, hb, colbits);
+            else
+                sel_block<F, Q, true>(A, j, nst, C, a, b, nth, rm, ri, hb, colbits);
+            kill_columns(A.alive, j, colbits);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(rm[q] > F(0)));
-        ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, false);
-        j = jn;
-        go = sync_rows_with<Q>(A.alive, rbase, word, dm);
-        ++nblk;
+            for (int q = 0; q < Q; ++q) dm[q] |= uniform64(__ballot(rm[q] > F(0)));
+            ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, false);
+            j += nst;
+            go = sync_rows_with<Q>(A.alive, rbase, word, dm);
+            ++nblk;
+        }
     }
     if (work && lane == 0 && nblk) atomicAdd(work, nblk);
     // rows still alive: their largest correlation over this item's columns
@@ -1244,15 +1208,16 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         for (int q = 0; q < Q; ++q) all &= dm[q];
         if (all == ~0ull) return;
     }
-    double* xs = lds;
-    double* ys = lds + sweep_xs_doubles(m);  // win; the skewed rows before the sweep
+    double* xp = lds;
+    double* ws = lds + hk_vp_doubles(m);
     H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R));
     double Sx, Sy;
     double C[Q];
-    item_start<Q>(A.T, A.mu, m, i0, jbeg, xs, ys, Sx, Sy, C);
+    item_start<Q>(A.T, A.mu, m, i0, jbeg, xp, ws, (double*)hs, Sx, Sy, C);
     double a[Q], b[Q], mx[Q];
     int32_t ri[Q];
-    double* rowinv = lds + sweep_rowv_offset(m, R);  // 1/(sqrt(m) sigma_i) of the lane's rows
+    // 1/(sqrt(m) sigma_i) of the lane's rows
+    double* rowinv = lds + sweep_rowv_offset(m, R, (int)sizeof(double));
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int64_t i = rbase + q;
@@ -1275,30 +1240,31 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     unsigned long long ev = pair_count(i0, std::min<int64_t>(i0 + R, N), jbeg, 1, m, left);
     int64_t j = jbeg + 1;
     bool go = true;
-    Prefetch<double> pf;
-    if (j < jend) prefetch<double>(pf, A.T, A.mu, A.df, A.dg, A.inv, j);
     while (go && j < jend) {
-        const int nst = (int)std::min<int64_t>(64, jend - j);
-        commit<double>(pf, A.T, m, j, xs, Sx, ys, hs);
-        if (j + nst < jend) prefetch<double>(pf, A.T, A.mu, A.df, A.dg, A.inv, j + nst);
-        const unsigned long long word = load_word(&A.alive[rbase >> 6]);
-        bool full;
-        if (left) full = (i0 - (j + nst - 1)) >= m;
-        else full = (j - (i0 + R - 1)) >= m;
-        if (full && nst == 64) ref_block_full<Q>(C, a, b, mx, hs);
-        else if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, hs);
-        else if (left) ref_block<Q, 2>(A, j, nst, C, a, b, mx, ri, hs);
-        else ref_block<Q, 1>(A, j, nst, C, a, b, mx, ri, hs);
-        ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, left);
-        j += nst;
-        if (prune) {
+        stage_batch<double>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
+        const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+        for (int sb = 0; go && j < jb_end; ++sb) {
+            const int nst = (int)std::min<int64_t>(64, jb_end - j);
+            const H4<double>* hb = hs + 64 * sb;
+            const unsigned long long word = load_word(&A.alive[rbase >> 6]);
+            bool full;
+            if (left) full = (i0 - (j + nst - 1)) >= m;
+            else full = (j - (i0 + R - 1)) >= m;
+            if (full && nst == 64) ref_block_full<Q>(C, a, b, mx, hb);
+            else if (full) ref_block<Q, 0>(A, j, nst, C, a, b, mx, ri, hb);
+            else if (left) ref_block<Q, 2>(A, j, nst, C, a, b, mx, ri, hb);
+            else ref_block<Q, 1>(A, j, nst, C, a, b, mx, ri, hb);
+            ev += pair_count(i0, std::min<int64_t>(i0 + R, N), j, nst, m, left);
+            j += nst;
+            if (prune) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const double iv = rowinv[Q * lane + q];
-                dm[q] |= uniform64(__ballot(iv > 0.0 && mx[q] * iv > thr));
+                for (int q = 0; q < Q; ++q) {
+                    const double iv = rowinv[Q * lane + q];
+                    dm[q] |= uniform64(__ballot(iv > 0.0 && mx[q] * iv > thr));
+                }
             }
+            go = sync_rows_with<Q>(A.alive, rbase, word, dm);
         }
-        go = sync_rows_with<Q>(A.alive, rbase, word, dm);
     }
     double invi[Q];
 #pragma unroll
@@ -1327,6 +1293,14 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
         }
     }
     evals += ev;
+}
+
+// The first local item of this workgroup in a series whose items start at
+// global number cum: the smallest it >= 0 with (cum + it) mod G = g.
+__device__ __forceinline__ unsigned long long first_item(unsigned long long cum)
+{
+    const unsigned long long G = gridDim.x;
+    return ((unsigned long long)blockIdx.x + G - cum % G) % G;
 }
 
 // First selection pass: every row tile's nearest near_cols columns, split
@@ -1399,23 +1373,25 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
-    for (int t = 0; t < B; ++t) {
-        const int b = (int)((blockIdx.x + (unsigned int)t) % (unsigned int)B);
+    // Items are dealt out statically: the items of series b get the global
+    // numbers cum_b + it (cum_b = items of the series before it) and
+    // workgroup g takes the global numbers g, g + G, ...  (a shared queue
+    // counter would cost one serialised device-scope atomic per item).
+    unsigned long long cum = 0;
+    for (int b = 0; b < B; ++b) {
         const SeriesDev& s = S[b];
         Ctrl* c = s.ctrl;
         if (!c->active || !c->prune) continue;
         const unsigned int nlive = c->nlive_sel;
         const unsigned long long total = (unsigned long long)nlive * c->maxc_sel;
         if (total == 0) continue;
+        const unsigned long long first = first_item(cum);
+        cum += total;
         const SweepArgs<F> A = args_of<F>(s, c);
         const F thr = sel_threshold<F>(c);
         const int32_t* __restrict__ tiles = s.tsel;
         unsigned long long ev = 0;
-        for (;;) {
-            unsigned long long it = 0;
-            if (threadIdx.x == 0) it = atomicAdd(&c->ctr_sel, 1ull);
-            it = uniform64(it);
-            if (it >= total) break;
+        for (unsigned long long it = first; it < total; it += gridDim.x) {
             const unsigned long long cc = it / nlive;
             const unsigned int p = (unsigned int)(it % nlive);
             const int64_t i0 = (int64_t)tiles[p] * R;
@@ -1434,62 +1410,109 @@ __global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
 
 // Live-tile lists.  mode 0: selection tiles (R rows), chunks to the right
 // beyond the first pass; mode 1: refinement tiles, chunks on both sides.
-__global__ void k_tiles(SeriesDev* S, int B, const int64_t* __restrict__ pfx, int R, int mode,
-                        int near_cols, int chunk, int near_rows)
+// One thread per tile; the block's live tiles are compacted with wave
+// ballots and a prefix over the block's waves, so each block makes one
+// atomic per counter (device-scope atomics on one address serialise).
+constexpr int TILES_BLOCK = 256;
+__global__ __launch_bounds__(TILES_BLOCK) void k_tiles(SeriesDev* S, int B,
+                                                       const int64_t* __restrict__ pfx, int R,
+                                                       int mode, int near_cols, int chunk,
+                                                       int near_rows)
 {
+    constexpr int NW = TILES_BLOCK / 64;
+    __shared__ unsigned int wn[NW], wmax[NW];
+    __shared__ unsigned long long wrows[NW];
+    __shared__ unsigned int base_s;
     const int b = series_of(pfx, B, blockIdx.x);
     const SeriesDev& s = S[b];
     Ctrl* c = s.ctrl;
     if (!c->active) return;
     if (mode == 0 && !c->prune) return;
-    const int64_t t = (blockIdx.x - pfx[b]) * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t t = (blockIdx.x - pfx[b]) * (int64_t)TILES_BLOCK + threadIdx.x;
     const int32_t m = c->m;
     const int64_t N = s.n - m + 1;
     const int64_t ntiles = (N + R - 1) / R;
-    if (t >= ntiles) return;
     const int words = R / 64;
-    unsigned long long any = 0ull;
     unsigned int cnt = 0;
-    for (int w = 0; w < words; ++w) {
-        const unsigned long long v = s.alive[t * words + w];
-        any |= v;
-        cnt += (unsigned int)__popcll(v);
-    }
-    if (!any) return;
-    atomicAdd(mode == 0 ? &c->rows_near : &c->rows_far, (unsigned long long)cnt);
-    if (mode == 1) atomicAdd(&c->live_ref, cnt);
-    const int64_t i0 = t * R;
-    int64_t nch;
+    int64_t nch = 0;
     bool both = true;
-    if (mode == 0) {
-        // the first pass covered near_cols columns from its own tile's start
-        const int64_t j0 = (i0 / near_rows) * near_rows + m + near_cols;
-        nch = j0 >= N ? 0 : (N - j0 + chunk - 1) / chunk;
-    } else {
-        const int64_t lend = std::min<int64_t>(N, i0 + R - m);
-        const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
-        const int64_t jr = i0 + m;
-        const int64_t nr = jr < N ? (N - jr + chunk - 1) / chunk : 0;
-        // The selection sweep covered the right side of every live row in
-        // FP32; a row's exact maximum there is within the guard g of the
-        // recorded one, so the right side needs the exact sweep only when
-        // some live row's recorded maximum is above thr64 - g (or when there
-        // was no selection sweep, or the round is an exact repeat, or a bare
-        // range search or a heatmap, which report every survivor's exact
-        // maximum).
-        both = !c->prune || c->exact_ref || c->mode == 3 || s.heat != nullptr;
-        if (!both) {
-            unsigned long long u = 0ull;
-            for (int w = 0; w < words; ++w) u |= s.alive[t * words + w] & s.unc[t * words + w];
-            both = u != 0ull;
+    if (t < ntiles) {
+        unsigned long long any = 0ull;
+        for (int q = 0; q < words; ++q) {
+            const unsigned long long v = s.alive[t * words + q];
+            any |= v;
+            cnt += (unsigned int)__popcll(v);
         }
-        nch = nl + (both ? nr : 0);
+        const int64_t i0 = t * R;
+        if (any == 0ull) {
+            nch = 0;
+        } else if (mode == 0) {
+            // the first pass covered near_cols columns from its own tile's start
+            const int64_t j0 = (i0 / near_rows) * near_rows + m + near_cols;
+            nch = j0 >= N ? 0 : (N - j0 + chunk - 1) / chunk;
+        } else {
+            const int64_t lend = std::min<int64_t>(N, i0 + R - m);
+            const int64_t nl = lend > 0 ? (lend + chunk - 1) / chunk : 0;
+            const int64_t jr = i0 + m;
+            const int64_t nr = jr < N ? (N - jr + chunk - 1) / chunk : 0;
+            // The selection sweep covered the right side of every live row in
+            // FP32; a row's exact maximum there is within the guard g of the
+            // recorded one, so the right side needs the exact sweep only when
+            // some live row's recorded maximum is above thr64 - g (or when
+            // there was no selection sweep, or the round is an exact repeat,
+            // or a bare range search or a heatmap, which report every
+            // survivor's exact maximum).
+            both = !c->prune || c->exact_ref || c->mode == 3 || s.heat != nullptr;
+            if (!both) {
+                unsigned long long u = 0ull;
+                for (int q = 0; q < words; ++q) u |= s.alive[t * words + q] & s.unc[t * words + q];
+                both = u != 0ull;
+            }
+            nch = nl + (both ? nr : 0);
+        }
     }
-    if (nch <= 0) return;
-    const unsigned int slot = atomicAdd(mode == 0 ? &c->nlive_sel : &c->nlive_ref, 1u);
-    // refinement entries carry bit 31 when only the left side is swept
-    (mode == 0 ? s.tsel : s.tref)[slot] = both ? (int32_t)t : (int32_t)((uint32_t)t | 0x80000000u);
-    atomicMax(mode == 0 ? &c->maxc_sel : &c->maxc_ref, (unsigned int)nch);
+    const bool entry = nch > 0;
+    // live rows and entries of the wave, then of the block
+    unsigned long long rows = cnt;
+    unsigned int mx = (unsigned int)nch;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        rows += __shfl_xor(rows, o);
+        mx = max(mx, (unsigned int)__shfl_xor((int)mx, o));
+    }
+    const unsigned long long bal = __ballot(entry);
+    if (lane == 0) {
+        wn[w] = (unsigned int)__popcll(bal);
+        wrows[w] = rows;
+        wmax[w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int tot = 0, mxb = 0;
+        unsigned long long rb = 0ull;
+        for (int q = 0; q < NW; ++q) {
+            tot += wn[q];
+            rb += wrows[q];
+            mxb = max(mxb, wmax[q]);
+        }
+        if (rb) {
+            atomicAdd(mode == 0 ? &c->rows_near : &c->rows_far, rb);
+            if (mode == 1) atomicAdd(&c->live_ref, (unsigned int)rb);
+        }
+        base_s = tot ? atomicAdd(mode == 0 ? &c->nlive_sel : &c->nlive_ref, tot) : 0u;
+        if (tot) atomicMax(mode == 0 ? &c->maxc_sel : &c->maxc_ref, mxb);
+    }
+    __syncthreads();
+    if (entry) {
+        unsigned int before = 0;
+        for (int q = 0; q < w; ++q) before += wn[q];
+        const unsigned int slot =
+            base_s + before + (unsigned int)__popcll(bal & ((1ull << lane) - 1ull));
+        // refinement entries carry bit 31 when only the left side is swept
+        (mode == 0 ? s.tsel : s.tref)[slot] =
+            both ? (int32_t)t : (int32_t)((uint32_t)t | 0x80000000u);
+    }
 }
 
 // Refinement: exact FP64 row maximum of rho over both sides for every tile
@@ -1500,24 +1523,22 @@ __global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_refine(SeriesDev* S, i
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
-    for (int t = 0; t < B; ++t) {
-        const int b = (int)((blockIdx.x + (unsigned int)t) % (unsigned int)B);
+    unsigned long long cum = 0;  // items dealt out as in k_select_far
+    for (int b = 0; b < B; ++b) {
         const SeriesDev& s = S[b];
         Ctrl* c = s.ctrl;
         if (!c->active || direct_round(c)) continue;
         const unsigned int nlive = c->nlive_ref;
         const unsigned long long total = (unsigned long long)nlive * c->maxc_ref;
         if (total == 0) continue;
+        const unsigned long long first = first_item(cum);
+        cum += total;
         const SweepArgs<double> A = args_of<double>(s, c);
         const double thr = c->thr64;
         const int prune = c->prune;
         const int32_t* __restrict__ tiles = s.tref;
         unsigned long long ev = 0;
-        for (;;) {
-            unsigned long long it = 0;
-            if (threadIdx.x == 0) it = atomicAdd(&c->ctr_ref, 1ull);
-            it = uniform64(it);
-            if (it >= total) break;
+        for (unsigned long long it = first; it < total; it += gridDim.x) {
             const unsigned long long cc = it / nlive;
             const unsigned int p = (unsigned int)(it % nlive);
             const int32_t e = tiles[p];
@@ -1800,8 +1821,6 @@ constexpr int PM_WAVES = POLISH_COLS / 128;   // waves per block
 constexpr int PM_CT = 8;                      // 16-column tiles per wave
 constexpr int PM_G = 16;                      // candidates per block
 constexpr int PM_KC = 128;                    // window offsets per LDS chunk
-typedef double pm_acc_t __attribute__((ext_vector_type(4)));
-
 __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
                                                           const int64_t* __restrict__ pfx)
 {
@@ -1819,7 +1838,7 @@ __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
     const int32_t m = c->m;
     const int64_t N = s.n - m + 1;
     const double* __restrict__ mu = cur_mu(s, c);
-    const double* __restrict__ var = cur_var(s, c);
+    const double* __restrict__ inv = s.inv64;  // 1/(sqrt(m) sigma), 0 for a flat window
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int ca = lane & 15, ka = lane >> 4;
     const int64_t blk = blockIdx.x - pfx[b];
@@ -1860,20 +1879,17 @@ __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
                 acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tb[k4 + 16 * ct], acc[ct], 0, 0, 0);
         }
     }
-    // epilogue: lane holds D[ka + 4 r][16 ct + ca]
-    const double feps = c->flat_eps;
+    // epilogue: lane holds D[ka + 4 r][16 ct + ca]; rho = C inv_i inv_j
     const double* __restrict__ sxs = xc + KP_MAX * stride;
     int64_t ci[4];
-    double sxv[4], sgi[4], best[4];
-    bool flat_i[4];
+    double sxv[4], ivi[4], best[4];
     long long bj[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int cid = min(g0 + ka + 4 * r, ncand - 1);
         ci[r] = s.cand[cid];
         sxv[r] = sxs[cid];
-        sgi[r] = sqrt(var[ci[r]]);
-        flat_i[r] = sgi[r] <= feps;
+        ivi[r] = inv[ci[r]];
         best[r] = -f_inf<double>();
         bj[r] = 0x7fffffffffffffffll;
     }
@@ -1882,17 +1898,16 @@ __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
     for (int ct = 0; ct < PM_CT; ++ct) {
         const int64_t j = j0 + colbase + 16 * ct + ca;
         if (j >= N) continue;
-        const double sgj = sqrt(var[j]), muj = mu[j];
-        const bool flat_j = sgj <= feps;
+        const double ivj = inv[j], muj = mu[j];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (j <= ci[r] - m || j >= ci[r] + m) {
                 double rh;
-                if (flat_i[r] || flat_j) {
-                    rh = (flat_i[r] && flat_j) ? 1.0 : 0.0;
+                if (ivi[r] == 0.0 || ivj == 0.0) {  // a flat window (R11)
+                    rh = (ivi[r] == 0.0 && ivj == 0.0) ? 1.0 : 0.0;
                 } else {
                     const double Cv = acc[ct][r] - muj * sxv[r];
-                    rh = fmin(1.0, fmax(-1.0, Cv / ((double)m * sgi[r] * sgj)));
+                    rh = fmin(1.0, fmax(-1.0, Cv * ivi[r] * ivj));
                 }
                 if (rh > best[r]) {  // a lane's columns ascend with ct: ties keep the smaller j
                     best[r] = rh;
@@ -2131,7 +2146,7 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
 template <typename F, int Q>
 static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, false);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(F), false);
     if (total[PFX_NEAR] == 0) return;
     cfg.timer->begin(0, st);
     hipLaunchKernelGGL((k_select_near<F, Q>), dim3((unsigned int)total[PFX_NEAR]), dim3(64), lds,
@@ -2142,8 +2157,8 @@ static void launch_near(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
 template <typename F, int Q>
 static void launch_far(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, false);
-    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TSEL]), dim3(256), 0, st, bt.s, bt.B,
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(F), false);
+    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TSEL]), dim3(TILES_BLOCK), 0, st, bt.s, bt.B,
                        bt.pfx[PFX_TSEL], 64 * Q, 0, cfg.near_cols, cfg.chunk_cols, 64 * cfg.q_near);
     cfg.timer->begin(1, st);
     hipLaunchKernelGGL((k_select_far<F, Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
@@ -2154,9 +2169,9 @@ static void launch_far(const Batch& bt, const SweepCfg& cfg, const int64_t* tota
 template <int Q>
 static void launch_refine(const Batch& bt, const SweepCfg& cfg, const int64_t* total, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TREF]), dim3(256), 0, st, bt.s, bt.B,
+    hipLaunchKernelGGL(k_tiles, dim3((unsigned int)total[PFX_TREF]), dim3(TILES_BLOCK), 0, st, bt.s, bt.B,
                        bt.pfx[PFX_TREF], 64 * Q, 1, 0, cfg.chunk_cols, 64 * cfg.q_near);
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, true);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(double), true);
     cfg.timer->begin(2, st);
     hipLaunchKernelGGL((k_refine<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, bt.B,
                        cfg.chunk_cols);

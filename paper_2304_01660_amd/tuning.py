@@ -25,8 +25,10 @@ import sys
 
 TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
 
-# (probe lengths, timed runs per configuration)
-PROBES = {"single": (8, 2), "batch": (12, 1)}
+# (probe lengths, timed runs per configuration).  The probe is the whole
+# length range: a probe of a series' first lengths is dominated by the first
+# length's range-halving searches and chose worse geometry than full runs.
+PROBES = {"single": (4096, 2), "batch": (4096, 1)}
 
 BATCH_NAME = "batch64_rw+ecg_n1e4-2e5_m(50..100)+50_k1_fp32"
 
