@@ -13,8 +13,8 @@ around its launches on the library's stream during instrumented steps), the
 per-length statistics kernel against the HBM roofline, legs on the other
 workloads (the 100k random walk, the 64-series batch against the plain
 per-series loop, forward + backward on the 200k random walk, the discord
-heatmap and the dense matrix profile) and the CPU oracle on a bounded sample
-of the headline workload.
+heatmap, the dense matrix profile and the streaming series) and the CPU
+oracle on a bounded sample of the headline workload.
 """
 
 from __future__ import annotations
@@ -371,6 +371,56 @@ def dense_leg(api, torch, w, T, tuned, ms_plain, reps: int = 3):
     }
 
 
+def ordered_pairs(n: int, m: int) -> int:
+    """Ordered non-self-match pairs (i, j), |i - j| >= m, among the
+    subsequences of length m of n points."""
+    N = n - m + 1
+    if N <= m:
+        return 0
+    return N * (N - 1) - 2 * ((m - 1) * N - m * (m - 1) // 2)
+
+
+def stream_leg(api, torch, dev, w, cuts, reps: int = 2):
+    """The series appended in pieces (streaming series): wall time of the
+    appends and of one top-k query, the pairs the appends add (every
+    ordered non-self pair of the final series, each evaluated once by the
+    FP64 band sweeps) and their rate against the VALU issue ceiling."""
+    T = torch.from_numpy(w.T).to(dev)
+    L = w.maxL - w.minL + 1
+    app_ms, q_ms = [], []
+    for rep in range(reps + 1):
+        st = api.Stream(w.n, w.minL, w.maxL, w.k, device=dev.index or 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            st.append(T[a:b])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = st.discords()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st.close()
+        if rep:  # the first pass warms up
+            app_ms.append((t1 - t0) * 1e3)
+            q_ms.append((t2 - t1) * 1e3)
+    pairs = sum(ordered_pairs(w.n, m) for m in range(w.minL, w.maxL + 1))
+    a = min(app_ms)
+    rate = pairs * OPS_PER_EVAL / (a * 1e-3) / 1e12
+    return {
+        "workload": w.name,
+        "appends": [b - a_ for a_, b in zip(cuts[:-1], cuts[1:])],
+        "append_ms_total": a,
+        "query_ms": min(q_ms),
+        "lengths_per_s_query": L / (min(q_ms) * 1e-3),
+        "pairs_added": pairs,
+        "pairs_per_s": pairs / (a * 1e-3),
+        "Tlane_ops_per_s": rate,
+        "frac_of_valu_peak": rate / VALU_PEAK_TOPS,
+        "top_k_as_oracle": None,
+        "_out": out,
+    }
+
+
 def measured_traffic(kernel: str, workload: str, options: dict):
     """HBM bytes per launch of `kernel` from the stored hardware-counter
     summary under profiles/, if it was taken on this exact kernel source,
@@ -452,6 +502,8 @@ def main():
                     help="skip the discord heatmap / interest leg")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense matrix-profile leg")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streaming-series leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (a known-size "
                          "reference for hardware traffic counters) and exit")
@@ -542,6 +594,12 @@ def main():
         if not args.no_dense:
             legs["dense_matrix_profile"] = dense_leg(api, torch, w2, plain2["T"], opts2,
                                                      plain2["ms_per_step"])
+        if not args.no_stream:
+            sl = stream_leg(api, torch, dev, w2, [0, 41_000, 70_500, w2.n])
+            out = sl.pop("_out")
+            out["count"] = torch.full((w2.maxL - w2.minL + 1,), w2.k, dtype=torch.int32)
+            sl["top_k_as_oracle"] = check_golden(out, golden_of("c2", w2))
+            legs["stream"] = sl
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, golden, args.cpu_budget)

@@ -354,6 +354,53 @@ int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t min
                         void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream);
 
 /*
+ * Streaming series (the paper's future work on series that grow or exceed
+ * one pass, Conclusions): a series of up to `capacity` points appended in
+ * pieces, with the top-k discords of every length in [minL, maxL] of the
+ * series so far available after any append.  The stream keeps one exact
+ * nearest-neighbour profile per length (Sec. 2.1, Eq. (1)-(5): for every
+ * subsequence the correlation of its nearest non-self match) and an append
+ * evaluates only the pairs it adds: every new subsequence (each reaches
+ * back over at most maxL - 1 points already there) against all
+ * subsequences, and every old subsequence against the new ones.  A query
+ * ranks each profile and recomputes the best rows with direct FP64 dot
+ * products, as a search does, so its rows equal those of palmad_discords()
+ * on the same points (the top-k of a length do not depend on MERLIN's
+ * range schedule).  No range r is involved: nothing is pruned.
+ *
+ * palmad_stream_workspace_size: bytes of device workspace for a stream
+ *   (pure host; PALMAD_EINVAL for arguments palmad_workspace_size() would
+ *   reject with n = capacity).  About 8 L bytes per point beyond a search's
+ *   workspace (L = maxL - minL + 1).
+ * palmad_stream_create: a stream on the context's device; workspace (device,
+ *   256-byte aligned) must stay valid and unused by anything else until
+ *   palmad_stream_destroy().  *out receives the handle (host memory).
+ * palmad_stream_append: appends values[0 .. count) (device, float64) and
+ *   updates every profile; PALMAD_EINVAL if the capacity would be exceeded,
+ *   PALMAD_ENONFINITE (stream unchanged) if a value is NaN or Inf.
+ * palmad_stream_discords: top-k rows of every length of the series so far,
+ *   laid out as palmad_discords() (idx, len, nn_dist, nn_idx: device,
+ *   [L * k]); requires at least 3 maxL - 1 points.
+ * palmad_stream_profile: the exact nearest-neighbour distance of every
+ *   subsequence of length m (nn_dist: device, float64[n - m + 1]).
+ * Calls are synchronous like the others; one stream is used by one host
+ * thread at a time.
+ */
+typedef struct palmad_stream palmad_stream;
+int palmad_stream_workspace_size(int64_t capacity, int32_t minL, int32_t maxL, int32_t k,
+                                 const palmad_options* opts, size_t* bytes);
+int palmad_stream_create(palmad_ctx* ctx, int64_t capacity, int32_t minL, int32_t maxL, int32_t k,
+                         const palmad_options* opts, void* workspace, size_t ws_bytes,
+                         palmad_stream** out, void* stream);
+int palmad_stream_append(palmad_stream* st, const double* values, int64_t count, void* stream);
+int palmad_stream_discords(palmad_stream* st, int64_t* idx, int32_t* len, double* nn_dist,
+                           int64_t* nn_idx, void* stream);
+int palmad_stream_profile(palmad_stream* st, int32_t m, double* nn_dist, void* stream);
+/* Points appended so far (-1 for NULL). */
+int64_t palmad_stream_length(const palmad_stream* st);
+void palmad_stream_destroy(palmad_stream* st);
+
+/*
  * For callers that cannot allocate device memory (code that must not call
  * hipMalloc or any allocating routine: tight serving loops, harnesses that
  * forbid allocation).  Same search and results as palmad_discords() with

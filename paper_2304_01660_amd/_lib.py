@@ -125,6 +125,15 @@ SIGNATURES = {
                                                _vp, _vp, _vp, _vp]),
     "palmad_window_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                            _vp, _vp]),
+    "palmad_stream_workspace_size": (ctypes.c_int, [_i64, _i32, _i32, _i32, ctypes.POINTER(Options),
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "palmad_stream_create": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, ctypes.POINTER(Options),
+                                            _vp, ctypes.c_size_t, ctypes.POINTER(_vp), _vp]),
+    "palmad_stream_append": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "palmad_stream_discords": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "palmad_stream_profile": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "palmad_stream_length": (_i64, [_vp]),
+    "palmad_stream_destroy": (None, [_vp]),
     "palmad_discords_static": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32,
                                               ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp,
                                               ctypes.POINTER(Stats), _vp]),

@@ -421,3 +421,68 @@ class DiscordNNDist(torch.autograd.Function):
 def discord_nn_dist(T: torch.Tensor, minL: int, maxL: int, k: int, **options):
     """Differentiable nnDist[L*k] of the top-k discords (see DiscordNNDist)."""
     return DiscordNNDist.apply(T, minL, maxL, k, options)[0]
+
+
+class Stream:
+    """A series that grows by appends (palmad_stream_*): after any append,
+    the top-k discords of every length of the series so far, equal to
+    ``discords`` on the same points, and the exact nearest-neighbour profile
+    of any length.  The device workspace is held until ``close``."""
+
+    def __init__(self, capacity: int, minL: int, maxL: int, k: int, device=None, **opts):
+        dev = torch.device("cuda", device if device is not None else torch.cuda.current_device())
+        self.device = dev
+        self.minL, self.maxL, self.k = int(minL), int(maxL), int(k)
+        o = _lib.make_options(**opts)
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().palmad_stream_workspace_size(int(capacity), self.minL, self.maxL,
+                                                            self.k, ctypes.byref(o),
+                                                            ctypes.byref(nbytes)))
+        self._ws = _workspace(int(nbytes.value), dev)
+        self._ctx = context(dev.index)
+        h = ctypes.c_void_p()
+        rc = _lib.lib().palmad_stream_create(self._ctx, int(capacity), self.minL, self.maxL, self.k,
+                                             ctypes.byref(o), ctypes.c_void_p(self._ws.data_ptr()),
+                                             self._ws.numel(), ctypes.byref(h), _stream(dev))
+        _lib.check(rc, self._ctx)
+        self._h = h
+
+    def __len__(self) -> int:
+        return int(_lib.lib().palmad_stream_length(self._h))
+
+    def append(self, values: torch.Tensor) -> None:
+        v = _series(values)
+        rc = _lib.lib().palmad_stream_append(self._h, ctypes.c_void_p(v.data_ptr()), v.shape[0],
+                                             _stream(self.device))
+        _lib.check(rc, self._ctx)
+
+    def discords(self) -> dict:
+        L = self.maxL - self.minL + 1
+        dev = self.device
+        out = {
+            "idx": torch.empty(L * self.k, dtype=torch.int64, device=dev),
+            "len": torch.empty(L * self.k, dtype=torch.int32, device=dev),
+            "nn_dist": torch.empty(L * self.k, dtype=torch.float64, device=dev),
+            "nn_idx": torch.empty(L * self.k, dtype=torch.int64, device=dev),
+        }
+        rc = _lib.lib().palmad_stream_discords(
+            self._h, *[ctypes.c_void_p(out[key].data_ptr()) for key in ("idx", "len", "nn_dist", "nn_idx")],
+            _stream(dev))
+        _lib.check(rc, self._ctx)
+        return out
+
+    def profile(self, m: int) -> torch.Tensor:
+        nn = torch.empty(len(self) - int(m) + 1, dtype=torch.float64, device=self.device)
+        rc = _lib.lib().palmad_stream_profile(self._h, int(m), ctypes.c_void_p(nn.data_ptr()),
+                                              _stream(self.device))
+        _lib.check(rc, self._ctx)
+        return nn
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.lib().palmad_stream_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        self.close()

@@ -607,6 +607,40 @@ int time_probe(palmad_ctx* ctx, const Probe& pr, int32_t k, const Opts& o, void*
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// streaming series
+// ---------------------------------------------------------------------------
+struct palmad_stream {
+    palmad_ctx* ctx;
+    Plan p;
+    Opts o;
+    void* ws;
+    unsigned long long* prof;  // per-length profiles [L][Npad] (ordered bits of rho)
+    int32_t* flag;             // device scratch for the finiteness check
+    int64_t cap, n;
+    int32_t minL, maxL, k;
+};
+
+namespace {
+
+// Workspace of a stream: the search layout of a series of `cap` points,
+// then the L profiles, then a small scratch.
+size_t stream_bytes(const Plan& p, int32_t L, size_t* off_prof, size_t* off_flag)
+{
+    *off_prof = al256(p.total);
+    *off_flag = al256(*off_prof + sizeof(unsigned long long) * (size_t)L * (size_t)p.lay[0].Npad);
+    return *off_flag + 256;
+}
+
+int stream_batch(palmad_stream* st, const Outputs* outs, Batch* bt)
+{
+    const double* none = nullptr;
+    return upload(st->ctx, st->p, st->ws, &none, outs, bt, &st->n);
+}
+
+}  // namespace
+
+
 extern "C" {
 
 const char* palmad_version(void) { return "palmad-mi355x 0.3 (gfx950)"; }
@@ -1104,5 +1138,159 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
 }
 
 
+
+int palmad_stream_workspace_size(int64_t capacity, int32_t minL, int32_t maxL, int32_t k,
+                                 const palmad_options* opts, size_t* bytes)
+{
+    if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
+    int rc = validate(nullptr, capacity, minL, maxL, k);
+    if (rc) return rc;
+    Opts o;
+    rc = read_opts(nullptr, opts, &o);
+    if (rc) return rc;
+    Plan p;
+    make_plan(1, &capacity, &minL, &maxL, k, cfg_of(o, nullptr), &p);
+    size_t a, b;
+    *bytes = stream_bytes(p, maxL - minL + 1, &a, &b);
+    return PALMAD_OK;
+}
+
+int palmad_stream_create(palmad_ctx* ctx, int64_t capacity, int32_t minL, int32_t maxL, int32_t k,
+                         const palmad_options* opts, void* workspace, size_t ws_bytes,
+                         palmad_stream** out, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!out) return fail(ctx, PALMAD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(ctx, capacity, minL, maxL, k);
+    if (rc) return rc;
+    Opts o;
+    rc = read_opts(ctx, opts, &o);
+    if (rc) return rc;
+    palmad_stream* st = new (std::nothrow) palmad_stream();
+    if (!st) return fail(ctx, PALMAD_ENOMEM, "stream allocation failed");
+    st->ctx = ctx;
+    st->o = o;
+    st->cap = capacity;
+    st->n = 0;
+    st->minL = minL;
+    st->maxL = maxL;
+    st->k = k;
+    make_plan(1, &capacity, &minL, &maxL, k, cfg_of(o, nullptr), &st->p);
+    size_t off_prof, off_flag;
+    const size_t need = stream_bytes(st->p, maxL - minL + 1, &off_prof, &off_flag);
+    rc = check_ws(ctx, workspace, ws_bytes, need);
+    if (rc) {
+        delete st;
+        return rc;
+    }
+    st->ws = workspace;
+    st->prof = (unsigned long long*)((char*)workspace + off_prof);
+    st->flag = (int32_t*)((char*)workspace + off_flag);
+    rc = enter(ctx, stream);
+    Batch bt;
+    if (!rc) rc = stream_batch(st, nullptr, &bt);
+    if (rc) {
+        delete st;
+        return rc;
+    }
+    const Layout& l = st->p.lay[0];
+    const hipError_t e1 = launch_ctrl_init(bt, ctx->work);
+    const hipError_t e2 = launch_fill_u64((unsigned long long*)((char*)workspace + st->p.base[0] + l.off_T),
+                                          l.Tlen, 0ull, ctx->work);
+    const hipError_t e3 = launch_fill_u64(st->prof, (int64_t)(maxL - minL + 1) * l.Npad,
+                                          0x000fffffffffffffull, ctx->work);  // -inf
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        delete st;
+        return fail(ctx, PALMAD_EDEVICE, "stream initialisation failed");
+    }
+    rc = leave(ctx, stream);
+    if (rc) {
+        delete st;
+        return rc;
+    }
+    *out = st;
+    return PALMAD_OK;
+}
+
+void palmad_stream_destroy(palmad_stream* st)
+{
+    if (!st) return;
+    (void)hipSetDevice(st->ctx->device);
+    (void)hipStreamSynchronize(st->ctx->work);
+    delete st;
+}
+
+int64_t palmad_stream_length(const palmad_stream* st) { return st ? st->n : -1; }
+
+int palmad_stream_append(palmad_stream* st, const double* values, int64_t count, void* stream)
+{
+    if (!st) return fail(nullptr, PALMAD_EINVAL, "stream is NULL");
+    palmad_ctx* ctx = st->ctx;
+    if (!values) return fail(ctx, PALMAD_EINVAL, "values is NULL");
+    if (count < 1) return fail(ctx, PALMAD_EINVAL, "count must be >= 1 (got %lld)", (long long)count);
+    if (count > st->cap - st->n)
+        return fail(ctx, PALMAD_EINVAL, "append of %lld points exceeds the capacity (%lld of %lld used)",
+                    (long long)count, (long long)st->n, (long long)st->cap);
+    int rc = enter(ctx, stream);
+    if (rc) return rc;
+    HIP_TRY(launch_check_finite(values, count, st->flag, ctx->work));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, st->flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    if (ctx->pinned[0]) return fail(ctx, PALMAD_ENONFINITE, "the appended values hold NaN or Inf");
+    const int64_t n_old = st->n;
+    st->n = n_old + count;
+    Batch bt;
+    rc = stream_batch(st, nullptr, &bt);
+    if (rc) {
+        st->n = n_old;
+        return rc;
+    }
+    SweepCfg cfg = cfg_of(st->o, nullptr);
+    HIP_TRY(launch_stream_append(bt, values, n_old, count, ctx->work));
+    HIP_TRY(launch_stream_update(bt, cfg, st->p.totals, st->minL, st->maxL, st->prof, n_old,
+                                 ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    return leave(ctx, stream);
+}
+
+int palmad_stream_discords(palmad_stream* st, int64_t* idx, int32_t* len, double* nn_dist,
+                           int64_t* nn_idx, void* stream)
+{
+    if (!st) return fail(nullptr, PALMAD_EINVAL, "stream is NULL");
+    palmad_ctx* ctx = st->ctx;
+    if (!idx || !len || !nn_dist || !nn_idx) return fail(ctx, PALMAD_EINVAL, "null output pointer");
+    int rc = validate(ctx, st->n, st->minL, st->maxL, st->k);
+    if (rc) return rc;
+    rc = enter(ctx, stream);
+    if (rc) return rc;
+    const Outputs out = {idx, len, nn_dist, nn_idx, nullptr};
+    Batch bt;
+    rc = stream_batch(st, &out, &bt);
+    if (rc) return rc;
+    HIP_TRY(launch_stream_query(bt, st->p.totals, st->minL, st->maxL, st->prof,
+                                64 * cfg_of(st->o, nullptr).q_near, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    return leave(ctx, stream);
+}
+
+int palmad_stream_profile(palmad_stream* st, int32_t m, double* nn_dist, void* stream)
+{
+    if (!st) return fail(nullptr, PALMAD_EINVAL, "stream is NULL");
+    palmad_ctx* ctx = st->ctx;
+    if (!nn_dist) return fail(ctx, PALMAD_EINVAL, "nn_dist is NULL");
+    if (m < st->minL || m > st->maxL)
+        return fail(ctx, PALMAD_EINVAL, "m (%d) outside [%d, %d]", m, st->minL, st->maxL);
+    int rc = validate(ctx, st->n, st->minL, st->maxL, 1);
+    if (rc) return rc;
+    rc = enter(ctx, stream);
+    if (rc) return rc;
+    Batch bt;
+    rc = stream_batch(st, nullptr, &bt);
+    if (rc) return rc;
+    HIP_TRY(launch_stream_profile(bt, st->p.totals, st->minL, m, st->prof, nn_dist, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    return leave(ctx, stream);
+}
 
 }  // extern "C"

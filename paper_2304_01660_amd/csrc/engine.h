@@ -216,6 +216,27 @@ hipError_t launch_adjoint(const double* Tpad, int64_t n, int64_t K, int32_t maxm
                           const Ctrl* ctrl, double* part, int64_t nblk, double* grad,
                           int64_t* jstar, hipStream_t st);
 
+// Streaming series (single series, bt.s[0].n = current length): profile
+// updates after an append from n_old points, the top-k rows of every length
+// from the profiles, one length's profile as distances, and a fill.
+hipError_t launch_stream_update(const Batch& bt, const SweepCfg& cfg, const int64_t* total,
+                                int32_t minL, int32_t maxL, unsigned long long* prof,
+                                int64_t n_old, hipStream_t st);
+hipError_t launch_stream_query(const Batch& bt, const int64_t* total, int32_t minL, int32_t maxL,
+                               const unsigned long long* prof, int hot_rows, hipStream_t st);
+hipError_t launch_stream_profile(const Batch& bt, const int64_t* total, int32_t minL, int32_t m,
+                                 const unsigned long long* prof, double* nn, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v,
+                           hipStream_t st);
+// Control blocks, histories, counters and bitmaps of every series to zero.
+hipError_t launch_ctrl_init(const Batch& bt, hipStream_t st);
+// Appended values: out[0] = 1 if any of src[0 .. count) is not finite.
+hipError_t launch_check_finite(const double* src, int64_t count, int32_t* out, hipStream_t st);
+// Copy src[0 .. count) into the padded series at n_old and recompute the
+// series' population sigma (flat threshold) over its first s.n points.
+hipError_t launch_stream_append(const Batch& bt, const double* src, int64_t n_old, int64_t count,
+                                hipStream_t st);
+
 // Device helper: series owning flat block `blk` (binary search over pfx).
 __device__ __forceinline__ int series_of(const int64_t* pfx, int B, int64_t blk)
 {

@@ -2141,6 +2141,129 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// streaming series: exact nearest-neighbour profiles per length, updated by
+// the pairs each append adds (the discord definition, Sec. 2.1, applied to a
+// series that grows; the top-k of a length are then those of its profile)
+// ---------------------------------------------------------------------------
+// After an append from n_old to n points, the subsequences of length m that
+// start at i >= N_old = n_old - m + 1 are new; each reaches back over at most
+// m - 1 points that were already there (the halo).  The pairs the append
+// adds are (new row, any column) and (old row, new column):
+//   part A  the row tiles from the one holding N_old sweep every column,
+//           both sides (left-side and right-side chunks alternate, nearest
+//           first);
+//   part B  the row tiles holding old rows sweep the new columns (right
+//           side only: every new column is to the right of every old row).
+// Rows of part A's first tile below N_old are swept again in full, which
+// only re-derives their maxima.  The refinement sweep does the work with
+// pruning off; every row's running maximum of rho stays in its length's
+// profile (ordered bits, prof[(m - minL) Npad + i]).
+template <int Q>
+__global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_stream_band(SeriesDev* S,
+                                                                      unsigned long long* prof,
+                                                                      int64_t n_old, int chunk)
+{
+    extern __shared__ double lds[];
+    constexpr int R = 64 * Q;
+    const SeriesDev& s = S[0];
+    Ctrl* c = s.ctrl;
+    SweepArgs<double> A = args_of<double>(s, c);
+    A.rho = prof + (int64_t)c->li * s.Npad;
+    const int32_t m = A.m;
+    const int64_t N = A.N;
+    const int64_t Nold = std::max<int64_t>(0, n_old - m + 1);
+    if (Nold >= N) return;
+    const int64_t a0 = (Nold / R) * R;
+    const int64_t tA = (N - a0 + R - 1) / R;
+    const int64_t cA = (N + chunk - 1) / chunk;
+    const int64_t itemsA = tA * 2 * cA;
+    const int64_t tB = (Nold + R - 1) / R;
+    const int64_t cB = (N - Nold + chunk - 1) / chunk;
+    const int64_t total = itemsA + tB * cB;
+    unsigned long long ev = 0;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        int64_t i0, jbeg, jend;
+        bool left;
+        if (it < itemsA) {
+            const int64_t t = it % tA, r = it / tA;
+            const int64_t cc = r >> 1;
+            left = (r & 1) != 0;
+            i0 = a0 + t * R;
+            if (left) {
+                jend = std::min<int64_t>(N, i0 + R - m) - cc * chunk;
+                jbeg = std::max<int64_t>(0, jend - chunk);
+            } else {
+                jbeg = i0 + m + cc * chunk;
+                jend = std::min<int64_t>(N, jbeg + chunk);
+            }
+        } else {
+            const int64_t x = it - itemsA;
+            const int64_t t = x % tB, cc = x / tB;
+            i0 = t * R;
+            left = false;
+            jbeg = std::max<int64_t>(Nold, i0 + m) + cc * chunk;
+            jend = std::min<int64_t>(N, jbeg + chunk);
+        }
+        if (jbeg >= jend) continue;
+        ref_item<Q>(A, i0, jbeg, jend, left, 2.0, 0, lds, ev);
+    }
+    if (threadIdx.x == 0 && ev)
+        atomicAdd(&s.evc[EV_REF * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
+}
+
+// A query at the current length: the profile becomes the round's row
+// maxima and every subsequence a live candidate (no pruning), so that
+// k_select_top, k_polish and k_round_end rank the profile, recompute the
+// best candidates exactly and write the length's top-k rows, as in a search
+// round without pruning.
+__global__ void k_stream_query(SeriesDev* S, const unsigned long long* __restrict__ prof)
+{
+    const SeriesDev& s = S[0];
+    Ctrl* c = s.ctrl;
+    const int64_t N = s.n - c->m + 1;
+    const unsigned long long* p = prof + (int64_t)c->li * s.Npad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.Npad;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s.rho[i] = i < N ? p[i] : 0x000fffffffffffffull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->mode = 3;
+        c->r = 0.0;
+        c->prune = 0;
+        c->thr64 = c->thr_sel = 2.0;
+        c->thr32 = 2.0f;
+        c->exact_ref = 0;
+        c->band_over = 0;
+        c->live_ref = 0xffffffffu;  // not a direct round
+        c->nsurv = c->ncand = 0;
+        c->done = 0;
+    }
+}
+
+// The exact profile of the current length as distances (Eq. (6)):
+// nn[i] = sqrt(2m (1 - rho_i)) for i < N.
+__global__ void k_stream_profile(SeriesDev* S, const unsigned long long* __restrict__ prof,
+                                 double* nn)
+{
+    const SeriesDev& s = S[0];
+    const Ctrl* c = s.ctrl;
+    const int32_t m = c->m;
+    const int64_t N = s.n - m + 1;
+    const unsigned long long* p = prof + (int64_t)c->li * s.Npad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double rh = dbl_of(p[i]);
+        nn[i] = sqrt(fmin(4.0 * (double)m, fmax(0.0, 2.0 * (double)m * (1.0 - rh))));
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t count, unsigned long long v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <typename F, int Q>
@@ -2227,6 +2350,69 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
     cfg.timer->end(3, st);
     hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining,
                        64 * cfg.q_near);
+    return hipGetLastError();
+}
+
+__global__ void k_set_len(SeriesDev* S, int32_t m, int32_t new_len);
+
+// Streaming: one append's profile updates at every length (statistics,
+// helpers, band sweeps), a query's top-k rows at every length, the profile
+// of one length, and the reset of every profile.
+template <int Q>
+static void launch_band(const Batch& bt, const SweepCfg& cfg, unsigned long long* prof,
+                        int64_t n_old, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(double), true);
+    hipLaunchKernelGGL((k_stream_band<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, prof, n_old,
+                       cfg.chunk_cols);
+}
+
+hipError_t launch_stream_update(const Batch& bt, const SweepCfg& cfg, const int64_t* total,
+                                int32_t minL, int32_t maxL, unsigned long long* prof,
+                                int64_t n_old, hipStream_t st)
+{
+    for (int32_t m = minL; m <= maxL; ++m) {
+        hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, m, m == minL ? 2 : 1);
+        hipLaunchKernelGGL(k_length, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
+                           bt.pfx[PFX_ELEM]);
+        switch (cfg.q_ref) {
+        case 4: launch_band<4>(bt, cfg, prof, n_old, st); break;
+        case 8: launch_band<8>(bt, cfg, prof, n_old, st); break;
+        default: launch_band<2>(bt, cfg, prof, n_old, st); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_query(const Batch& bt, const int64_t* total, int32_t minL, int32_t maxL,
+                               const unsigned long long* prof, int hot_rows, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_KC + POLISH_COLS + bt.maxL_all + 4);
+    for (int32_t m = minL; m <= maxL; ++m) {
+        hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, m, m == minL ? 2 : 1);
+        hipLaunchKernelGGL(k_length, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
+                           bt.pfx[PFX_ELEM]);
+        hipLaunchKernelGGL(k_stream_query, dim3(256), dim3(256), 0, st, bt.s, prof);
+        hipLaunchKernelGGL(k_select_top, dim3(1), dim3(TOPK_BLOCK), 0, st, bt.s);
+        hipLaunchKernelGGL(k_polish, dim3((unsigned int)total[PFX_POLISH], (KP_MAX + PM_G - 1) / PM_G),
+                           dim3(64 * PM_WAVES), lds, st, bt.s, 1, bt.pfx[PFX_POLISH]);
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(END_BLOCK), 0, st, bt.s, bt.remaining, hot_rows);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_profile(const Batch& bt, const int64_t* total, int32_t minL, int32_t m,
+                                 const unsigned long long* prof, double* nn, hipStream_t st)
+{
+    const hipError_t e = launch_stats_to(bt, minL, m, total, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stream_profile, dim3(256), dim3(256), 0, st, bt.s, prof, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, st, p, count, v);
     return hipGetLastError();
 }
 

@@ -110,6 +110,12 @@ __global__ void k_sigma_final(SeriesDev* S)
     }
 }
 
+hipError_t launch_ctrl_init(const Batch& bt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctrl_init, dim3(64, bt.B), dim3(256), 0, st, bt.s);
+    return hipGetLastError();
+}
+
 hipError_t launch_prepare(const Batch& bt, const int64_t* total, hipStream_t st)
 {
     (void)total;
@@ -117,6 +123,59 @@ hipError_t launch_prepare(const Batch& bt, const int64_t* total, hipStream_t st)
     hipLaunchKernelGGL(k_copy_sum, dim3(RED_BLOCKS, bt.B), dim3(RED_THREADS), 0, st, bt.s);
     hipLaunchKernelGGL(k_sqdev, dim3(RED_BLOCKS, bt.B), dim3(RED_THREADS), 0, st, bt.s);
     hipLaunchKernelGGL(k_sigma_final, dim3(bt.B), dim3(64), 0, st, bt.s);
+    return hipGetLastError();
+}
+
+// Streaming appends (one series): the appended values' finiteness, their
+// copy into the padded series at n_old, and the sum of the first s.n values
+// in the same order as k_copy_sum, so that sigma of the series (hence the
+// flat threshold) equals that of a search over the same values.
+__global__ void k_check_finite(const double* __restrict__ src, int64_t count, int32_t* out)
+{
+    __shared__ int bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) bad |= !isfinite(src[i]);
+    if (bad) atomicOr(&bad_s, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = bad_s;
+}
+
+__global__ void k_stream_copy(SeriesDev* S, const double* __restrict__ src, int64_t n_old,
+                              int64_t count)
+{
+    const SeriesDev& s = S[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s.T[n_old + i] = src[i];
+}
+
+__global__ void k_stream_sum(SeriesDev* S)
+{
+    const SeriesDev& s = S[0];
+    __shared__ double sh[16];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride)
+        acc += s.T[i];
+    const double t = block_sum_p(acc, sh);
+    if (threadIdx.x == 0) s.red[blockIdx.x] = t;
+}
+
+hipError_t launch_check_finite(const double* src, int64_t count, int32_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(1024), 0, st, src, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_append(const Batch& bt, const double* src, int64_t n_old, int64_t count,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stream_copy, dim3(256), dim3(256), 0, st, bt.s, src, n_old, count);
+    hipLaunchKernelGGL(k_stream_sum, dim3(RED_BLOCKS, 1), dim3(RED_THREADS), 0, st, bt.s);
+    hipLaunchKernelGGL(k_sqdev, dim3(RED_BLOCKS, 1), dim3(RED_THREADS), 0, st, bt.s);
+    hipLaunchKernelGGL(k_sigma_final, dim3(1), dim3(64), 0, st, bt.s);
     return hipGetLastError();
 }
 

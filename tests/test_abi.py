@@ -138,3 +138,28 @@ def test_batched_offsets_must_start_at_zero():
     b = ctypes.c_size_t(0)
     assert _lib.lib().palmad_batched_workspace_size(1, offs, lo, hi, 1, None, ctypes.byref(b)) == -1
     assert _lib.lib().palmad_batched_workspace_size(1, None, lo, hi, 1, None, ctypes.byref(b)) == -1
+
+
+def test_stream_workspace_size_validates_and_grows_with_lengths():
+    L = _lib.lib()
+    o = _lib.make_options()
+    b = ctypes.c_size_t(0)
+    assert L.palmad_stream_workspace_size(100, 10, 34, 1, ctypes.byref(o), ctypes.byref(b)) == -1
+    assert L.palmad_stream_workspace_size(10**5, 2, 34, 1, ctypes.byref(o), ctypes.byref(b)) == -1
+    assert L.palmad_stream_workspace_size(10**5, 64, 64, 3, ctypes.byref(o), ctypes.byref(b)) == 0
+    one = b.value
+    assert L.palmad_stream_workspace_size(10**5, 64, 128, 3, ctypes.byref(o), ctypes.byref(b)) == 0
+    # one profile of 8 bytes per subsequence and length beyond a search's workspace
+    assert b.value - one >= 8 * 64 * (10**5 - 128)
+    ws = ctypes.c_size_t(0)
+    assert L.palmad_workspace_size(10**5, 64, 128, 3, ctypes.byref(o), ctypes.byref(ws)) == 0
+    assert b.value > ws.value
+
+
+def test_stream_calls_reject_null_handles():
+    L = _lib.lib()
+    assert L.palmad_stream_append(None, None, 1, None) == -1
+    assert L.palmad_stream_discords(None, None, None, None, None, None) == -1
+    assert L.palmad_stream_profile(None, 10, None, None) == -1
+    assert L.palmad_stream_length(None) == -1
+    L.palmad_stream_destroy(None)
