@@ -80,44 +80,84 @@ def golden_of(tag, w):
     return json.load(open(path)) if os.path.exists(path) else None
 
 
+def merlin_calls(w, golden):
+    """Every DRAG call of the oracle's MERLIN run on this workload, as
+    (length index, r), rebuilt from the stored per-length results with the
+    rules of Alg. 1 (first length: 2 sqrt(minL), halved after a failure;
+    next four: 0.99 nnDist(m - 1), times 0.99 after a failure; later: mean -
+    2 sd of the last five nnDist, lowered by sd after a failure; nnDist(m) =
+    the k-th reported distance).  Each length's last r is checked against
+    the stored one."""
+    import math
+
+    L = w.maxL - w.minL + 1
+    k = w.k
+    hist = [golden["nn"][li * k + k - 1] for li in range(L)]
+    calls = []
+    for li in range(L):
+        nc = golden["calls"][li]
+        if li == 0:
+            rs = [2.0 * math.sqrt(w.minL) * 0.5 ** c for c in range(nc)]
+        elif li <= 4:
+            rs = [0.99 * hist[li - 1] * 0.99 ** c for c in range(nc)]
+        else:
+            last = hist[li - 5:li]
+            mu = sum(last) / 5.0
+            sd = math.sqrt(sum((x - mu) ** 2 for x in last) / 5.0)
+            r, rs = mu - 2.0 * sd, []
+            for c in range(nc):
+                rs.append(r)
+                r = r - sd if sd > 0.0 else 0.99 * r
+        if abs(rs[-1] - golden["r"][li]) > 1e-9 * max(1.0, abs(golden["r"][li])):
+            return None
+        calls += [(li, r) for r in rs]
+    return calls
+
+
 def cpu_baseline(w, golden, budget_s: float):
-    """The oracle's DRAG (serial, FP64) at MERLIN's own final r for lengths
-    spread over the range, until the time budget is spent.  At each of these
-    lengths the oracle's MERLIN made exactly one DRAG call (recorded in the
-    stored result), so the sample is that part of its run; the first length's
-    r search (several DRAG calls) is not sampled, and the full run's own
-    wall time is reported beside it."""
+    """The oracle (serial FP64 DRAG, oracle/merlin.c) on a stratified sample
+    of the DRAG calls its MERLIN run makes on this workload (failed attempts
+    and the first length's range halving included, rebuilt from the stored
+    result), until the time budget is spent; lengths/s = lengths / (mean
+    sampled call time x number of calls).  The full run's own wall time,
+    taken when the stored result was written, is reported beside it."""
     import oracle
 
     if golden is None:
         return None
     L = w.maxL - w.minL + 1
-    single = [li for li in range(1, L) if golden["calls"][li] == 1]
-    # stratified order: middle, then halves, quarters, ...
+    calls = merlin_calls(w, golden)
+    if calls is None:
+        return None
+    # stratified order over the calls: middle, then halves, quarters, ...
     order, seen = [], set()
-    for step in (2, 4, 8, 16, 32, 64, 128):
+    for step in (2, 4, 8, 16, 32, 64, 128, 256):
         for q in range(1, step, 2):
-            li = single[min(len(single) - 1, q * len(single) // step)]
-            if li not in seen:
-                seen.add(li)
-                order.append(li)
+            c = min(len(calls) - 1, q * len(calls) // step)
+            if c not in seen:
+                seen.add(c)
+                order.append(c)
+    order = [0] + [c for c in order if c != 0]  # the first call (largest r) too
     t0 = time.perf_counter()
     done = []
-    for li in order:
-        oracle.drag(w.T, w.minL + li, golden["r"][li])
-        done.append(w.minL + li)
+    for c in order:
+        li, r = calls[c]
+        oracle.drag(w.T, w.minL + li, r)
+        done.append((w.minL + li, round(r, 4)))
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    est = dt / len(done) * len(calls)
     full_s = golden.get("oracle_seconds")
     return {
-        "value": len(done) / dt,
+        "value": L / est,
         "unit": "lengths/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"serial FP64 DRAG of the oracle (oracle/merlin.c) at MERLIN's final r for "
-                   f"lengths {done} of the same series, {dt:.1f} s; MERLIN made one DRAG call at "
-                   f"each of them; the first length's r search is not in the sample"),
+        "sample": (f"serial FP64 DRAG of the oracle (oracle/merlin.c): {len(done)} of the "
+                   f"{len(calls)} DRAG calls of its MERLIN run on the same series, as (m, r) "
+                   f"{done}, {dt:.1f} s; lengths/s = {L} lengths / (mean call time x "
+                   f"{len(calls)} calls)"),
         "host_cpu": host_cpu(),
         "full_run": {
             "seconds": full_s,

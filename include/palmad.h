@@ -69,7 +69,7 @@ typedef struct {
                               0 = 32. */
     float guard;           /* correlation guard band of the FP32 selection sweep:
                               a pair prunes only if its FP32 correlation exceeds the
-                              threshold by more than this.  <= 0 = 1e-4. */
+                              threshold by more than this.  <= 0 = 1.25e-4. */
     int32_t near_cols;     /* columns scanned by the first selection pass of a row
                               tile (in chunks of chunk_cols run concurrently) before
                               the remaining columns go to the queued pass; 0 = 2048.
@@ -352,6 +352,25 @@ int palmad_discords_backward(palmad_ctx* ctx, const double* T, int64_t n, int64_
  */
 int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
                         void* workspace, size_t ws_bytes, double* mu, double* sigma, void* stream);
+
+/*
+ * Diagnostic of the FP32 selection sweep's soundness (Sec. 3.2 run in FP32
+ * with a guard band): over `items` work items of 512-row tiles (the longest
+ * recurrence chains any sweep runs) and `chunk` columns each, spread over
+ * the series at length m (items <= 0: every tile and chunk of the right
+ * side), the centred diagonal recurrence is run in FP32 exactly as the
+ * selection sweep runs it and in FP64 side by side.
+ *   *drift  the largest |rho_FP32 - rho_FP64| over the items' pairs (host);
+ *   *band   the guard band the selection sweep uses at this length for
+ *           `guard` (<= 0: the default), at least guard (host).
+ * Pruning in FP32 is sound while drift < band.  workspace: device, >=
+ * palmad_selection_drift_workspace_size() bytes.  Requires 3 <= minL <= m,
+ * n >= 3 m - 1, chunk >= 8.
+ */
+int palmad_selection_drift_workspace_size(int64_t n, int32_t minL, int32_t m, size_t* bytes);
+int palmad_selection_drift(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
+                           int64_t items, int32_t chunk, float guard, void* workspace,
+                           size_t ws_bytes, double* drift, double* band, void* stream);
 
 /*
  * Streaming series (the paper's future work on series that grow or exceed

@@ -125,6 +125,12 @@ SIGNATURES = {
                                                _vp, _vp, _vp, _vp]),
     "palmad_window_stats": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                            _vp, _vp]),
+    "palmad_selection_drift_workspace_size": (ctypes.c_int, [_i64, _i32, _i32,
+                                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "palmad_selection_drift": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i64, _i32,
+                                              ctypes.c_float, _vp, ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), _vp]),
     "palmad_stream_workspace_size": (ctypes.c_int, [_i64, _i32, _i32, _i32, ctypes.POINTER(Options),
                                                     ctypes.POINTER(ctypes.c_size_t)]),
     "palmad_stream_create": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, ctypes.POINTER(Options),

@@ -423,6 +423,28 @@ def discord_nn_dist(T: torch.Tensor, minL: int, maxL: int, k: int, **options):
     return DiscordNNDist.apply(T, minL, maxL, k, options)[0]
 
 
+def selection_drift(T: torch.Tensor, minL: int, m: int, *, items: int = 2048, chunk: int = 512,
+                    guard: float = 0.0):
+    """(drift, band): the largest |rho_FP32 - rho_FP64| of the FP32 selection
+    recurrence over `items` sampled 512-row tiles of `chunk` columns at
+    length m, and the guard band the selection sweep uses there."""
+    T = _series(T)
+    dev = T.device
+    n = T.shape[0]
+    nb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().palmad_selection_drift_workspace_size(n, int(minL), int(m),
+                                                                ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), dev)
+    d, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    rc = _lib.lib().palmad_selection_drift(ctx, ctypes.c_void_p(T.data_ptr()), n, int(minL), int(m),
+                                           int(items), int(chunk), float(guard),
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                           ctypes.byref(d), ctypes.byref(b), _stream(dev))
+    _lib.check(rc, ctx)
+    return d.value, b.value
+
+
 class Stream:
     """A series that grows by appends (palmad_stream_*): after any append,
     the top-k discords of every length of the series so far, equal to

@@ -89,7 +89,7 @@ constexpr unsigned int KNOWN_FLAGS = PALMAD_FLAG_TIME_KERNELS | PALMAD_FLAG_NO_G
 
 int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 {
-    Opts r = {32, 1e-4f, 2048, 1024, 0u, 0, 0, 0, 2048};
+    Opts r = {32, 1.25e-4f, 2048, 1024, 0u, 0, 0, 0, 2048};
     if (o) {
         if (o->flags & ~KNOWN_FLAGS)
             return fail(ctx, PALMAD_EINVAL, "unknown option flags 0x%x", o->flags);
@@ -962,6 +962,53 @@ int palmad_window_stats(palmad_ctx* ctx, const double* T, int64_t n, int32_t min
     HIP_TRY(launch_stats_out(bt, n - m + 1, mu, sigma, ctx->work));
     HIP_TRY(hipStreamSynchronize(ctx->work));
     return leave(ctx, stream);
+}
+
+int palmad_selection_drift(palmad_ctx* ctx, const double* T, int64_t n, int32_t minL, int32_t m,
+                           int64_t items, int32_t chunk, float guard, void* workspace,
+                           size_t ws_bytes, double* drift, double* band, void* stream)
+{
+    if (!ctx) return fail(nullptr, PALMAD_EINVAL, "ctx is NULL");
+    if (!T || !drift || !band) return fail(ctx, PALMAD_EINVAL, "null input or output pointer");
+    int rc = validate(ctx, n, minL, m, 1);
+    if (rc) return rc;
+    if (chunk < 8) return fail(ctx, PALMAD_EINVAL, "need chunk >= 8");
+    Plan p;
+    make_plan(1, &n, &minL, &m, 1, cfg_of(default_opts(), nullptr), &p);
+    const size_t off_out = al256(p.total);
+    rc = check_ws(ctx, workspace, ws_bytes, off_out + 256);
+    if (rc) return rc;
+    rc = enter(ctx, stream);
+    if (rc) return rc;
+    Batch bt;
+    rc = upload(ctx, p, workspace, &T, nullptr, &bt);
+    if (rc) return rc;
+    rc = prepare(ctx, bt, p);
+    if (rc) return rc;
+    double* out = (double*)((char*)workspace + off_out);
+    HIP_TRY(launch_drift(bt, p.totals, minL, m, items, chunk, guard > 0.0f ? guard : 1.25e-4f, out,
+                         ctx->work));
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(ctx->pinned + 16, out, sizeof h, hipMemcpyDeviceToHost, ctx->work));
+    HIP_TRY(hipStreamSynchronize(ctx->work));
+    std::memcpy(h, ctx->pinned + 16, sizeof h);
+    // out[0] holds the ordered bits of a non-negative double: the bits themselves
+    const unsigned long long u = h[0];
+    const unsigned long long bits = (u & 0x8000000000000000ull) ? (u & ~0x8000000000000000ull) : ~u;
+    std::memcpy(drift, &bits, sizeof(double));
+    std::memcpy(band, &h[1], sizeof(double));
+    return leave(ctx, stream);
+}
+
+int palmad_selection_drift_workspace_size(int64_t n, int32_t minL, int32_t m, size_t* bytes)
+{
+    if (!bytes) return fail(nullptr, PALMAD_EINVAL, "bytes is NULL");
+    const int rc = validate(nullptr, n, minL, m, 1);
+    if (rc) return rc;
+    Plan p;
+    make_plan(1, &n, &minL, &m, 1, cfg_of(default_opts(), nullptr), &p);
+    *bytes = al256(p.total) + 256;
+    return PALMAD_OK;
 }
 
 int palmad_backward_workspace_size(int64_t n, int64_t K, int32_t maxm, size_t* bytes)

@@ -237,6 +237,12 @@ hipError_t launch_check_finite(const double* src, int64_t count, int32_t* out, h
 hipError_t launch_stream_append(const Batch& bt, const double* src, int64_t n_old, int64_t count,
                                 hipStream_t st);
 
+// Diagnostic: statistics up to length m, the guard band, then out[0] =
+// ordered bits of the largest |rho32 - rho64| of the FP32 selection
+// recurrence over nitems sampled items, out[1] = the band (a double).
+hipError_t launch_drift(const Batch& bt, const int64_t* total, int32_t minL, int32_t m,
+                        int64_t nitems, int chunk, float guard, double* out, hipStream_t st);
+
 // Device helper: series owning flat block `blk` (binary search over pfx).
 __device__ __forceinline__ int series_of(const int64_t* pfx, int B, int64_t blk)
 {

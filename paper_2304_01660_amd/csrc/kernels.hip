@@ -172,13 +172,16 @@ __device__ __forceinline__ unsigned long long pair_count(long long ilo, long lon
 // spread next to windows with a large one (within the R_MAX windows a chain
 // passes) amplify the covariance's absolute error.  With gamma the largest
 // ratio of the nearby largest spread to a window's own spread, the drift
-// measured over the configured workloads stays below
-//     2^-24 * sqrt(R_MAX) * gamma^2 / 2
-// (random walks, ECG-like series); the band is twice that, and never below
-// the caller's guard.  A series with an extreme spread contrast thus gets a
-// wide band (the selection sweep prunes less, the FP64 refinement decides),
-// never an unsound one.
-constexpr double GUARD_PER_CONTRAST2 = 2.0 * 0x1p-24 * 22.62741699796952;  // 2 u sqrt(512)
+// measured on the device (k_drift, thousands of sampled 512-row tiles, and
+// every tile of the smaller series) over the configured workloads stays
+// below
+//     2^-24 * sqrt(R_MAX) * gamma^2
+// (random walks, ECG-like series; ECG-like beats between quiet baselines
+// come closest); the band is four times that, and never below the caller's
+// guard (default 1.25e-4).  A series with an extreme spread contrast thus
+// gets a wide band (the selection sweep prunes less, the FP64 refinement
+// decides), never an unsound one.
+constexpr double GUARD_PER_CONTRAST2 = 4.0 * 0x1p-24 * 22.62741699796952;  // 4 u sqrt(512)
 
 __device__ __forceinline__ double sel_guard(const Ctrl* c, float guard)
 {
@@ -2141,6 +2144,114 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// diagnostic: drift of the FP32 selection recurrence from FP64
+// ---------------------------------------------------------------------------
+// Items of 512-row tiles (the longest recurrence chains any sweep runs) and
+// `chunk` columns to their right, spread over the series (tiles evenly,
+// columns at varying distance): the centred diagonal recurrence is run in
+// FP32 exactly as the selection sweep runs it (FP32 helpers, exact
+// boundary values rounded to FP32) and in FP64 (the refinement sweep's
+// arithmetic), side by side from the same exact first column.  The largest
+// |rho32 - rho64| over the items' non-self pairs (rho = C inv_i inv_j) goes
+// to out[0] (ordered bits, atomicMax).
+template <int U>
+__device__ __forceinline__ void drift_step(float (&C32)[8], double (&C64)[8], const float (&a32)[8],
+                                           const float (&b32)[8], const double (&a64)[8],
+                                           const double (&b64)[8], const H4<float>& h32,
+                                           const H4<double>& h64, const float (&iv32)[8],
+                                           const double (&iv64)[8], const int64_t (&ri)[8],
+                                           int64_t j, int32_t m, int64_t N, double& mx)
+{
+    advance<float, 8, U>(C32, a32, b32, h32.df, h32.dg, h32.B);
+    advance<double, 8, U>(C64, a64, b64, h64.df, h64.dg, h64.B);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (j - m >= ri[q] && ri[q] < N && j < N) {
+            const float r32 = C32[slot_reg<8, U>(q)] * h32.inv * iv32[q];
+            const double r64 = C64[slot_reg<8, U>(q)] * h64.inv * iv64[q];
+            mx = fmax(mx, fabs((double)r32 - r64));
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_drift(SeriesDev* S, int64_t nitems, int chunk,
+                                              unsigned long long* out)
+{
+    constexpr int Q = 8, R = 64 * Q;
+    extern __shared__ double lds[];
+    const SeriesDev& s = S[0];
+    Ctrl* c = s.ctrl;
+    const SweepArgs<float> A32 = args_of<float>(s, c);
+    const SweepArgs<double> A64 = args_of<double>(s, c);
+    const int32_t m = A64.m;
+    const int64_t N = A64.N;
+    const int lane = threadIdx.x;
+    double* xp = lds;
+    double* ws = lds + hk_vp_doubles(m);
+    H4<double>* hs64 = (H4<double>*)(lds + sweep_hs_offset(m, R));
+    H4<float>* hs32 = (H4<float>*)(lds + sweep_hs_offset(m, R) + sweep_hs_doubles(8));
+    const int64_t ntiles = (N + R - 1) / R;
+    // nitems <= 0: every (tile, chunk) of the right side, chunk-major
+    const int64_t nchall = (N + chunk - 1) / chunk;
+    const bool all = nitems <= 0;
+    const int64_t total = all ? ntiles * nchall : nitems;
+    double mx = 0.0;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int64_t i0 = uniform_i64(all ? (it % ntiles) * R : ((it * ntiles) / nitems) * R);
+        const int64_t span = N - (i0 + m);
+        if (span <= 0) continue;
+        const int64_t nch = std::max<int64_t>(1, span / chunk);
+        const int64_t cc = all ? it / ntiles : (it * 37) % nch;
+        if (all && cc * chunk >= span) continue;
+        const int64_t jbeg = uniform_i64(i0 + m + cc * chunk);
+        const int64_t jend = std::min<int64_t>(N, jbeg + 1 + chunk);
+        double Sx, Sy, acc[Q];
+        item_start<Q>(A64.T, A64.mu, m, i0, jbeg, xp, ws, (double*)hs64, Sx, Sy, acc);
+        float C32[Q], a32[Q], b32[Q], iv32[Q];
+        double C64[Q], a64[Q], b64[Q], iv64[Q];
+        int64_t ri[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t i = i0 + Q * lane + q;
+            const bool top = (lane == 0) && (q == 0);
+            const int64_t ip = top ? i : i - 1;
+            C64[q] = acc[q];
+            C32[q] = (float)acc[q];
+            a32[q] = top ? 0.0f : A32.df[ip];
+            b32[q] = top ? 0.0f : A32.dg[ip];
+            a64[q] = top ? 0.0 : A64.df[ip];
+            b64[q] = top ? 0.0 : A64.dg[ip];
+            iv32[q] = A32.inv[i];
+            iv64[q] = A64.inv[i];
+            ri[q] = i;
+        }
+        for (int64_t j = jbeg + 1; j + Q <= jend; ) {
+            stage_batch<double>(A64.T, A64.mu, A64.df, A64.dg, A64.inv, m, j, xp, Sx, ws, hs64);
+            stage_batch<float>(A32.T, A32.mu, A32.df, A32.dg, A32.inv, m, j, xp, Sx, ws, hs32);
+            const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+            for (int s0 = 0; j + Q <= jb_end; s0 += Q, j += Q) {
+#define DRIFT_STEP(U)                                                                          \
+    drift_step<U>(C32, C64, a32, b32, a64, b64, hs32[s0 + (U)], hs64[s0 + (U)], iv32, iv64, ri, \
+                  j + (U), m, N, mx);
+                DRIFT_STEP(0) DRIFT_STEP(1) DRIFT_STEP(2) DRIFT_STEP(3)
+                DRIFT_STEP(4) DRIFT_STEP(5) DRIFT_STEP(6) DRIFT_STEP(7)
+#undef DRIFT_STEP
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (lane == 0) atomicMax(out, ord_of(mx));
+}
+
+// The guard band the selection sweep uses at the current length (after
+// k_guard), as a double in out[1].
+__global__ void k_drift_band(SeriesDev* S, float guard, double* out)
+{
+    out[1] = sel_guard(S[0].ctrl, guard);
+}
+
+// ---------------------------------------------------------------------------
 // streaming series: exact nearest-neighbour profiles per length, updated by
 // the pairs each append adds (the discord definition, Sec. 2.1, applied to a
 // series that grows; the top-k of a length are then those of its profile)
@@ -2354,6 +2465,22 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
 }
 
 __global__ void k_set_len(SeriesDev* S, int32_t m, int32_t new_len);
+
+hipError_t launch_drift(const Batch& bt, const int64_t* total, int32_t minL, int32_t m,
+                        int64_t nitems, int chunk, float guard, double* out, hipStream_t st)
+{
+    const hipError_t e = launch_stats_to(bt, minL, m, total, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_guard, dim3(1), dim3(GUARD_BLOCK), 0, st, bt.s, guard);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)out, (int64_t)1,
+                       0ull);
+    const size_t lds = sizeof(double) * (sweep_hs_offset(bt.maxL_all, 512) + sweep_hs_doubles(8) +
+                                         sweep_hs_doubles(4));
+    hipLaunchKernelGGL(k_drift, dim3(1024), dim3(64), lds, st, bt.s, nitems, chunk,
+                       (unsigned long long*)out);
+    hipLaunchKernelGGL(k_drift_band, dim3(1), dim3(1), 0, st, bt.s, guard, out);
+    return hipGetLastError();
+}
 
 // Streaming: one append's profile updates at every length (statistics,
 // helpers, band sweeps), a query's top-k rows at every length, the profile

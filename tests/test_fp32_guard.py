@@ -9,7 +9,7 @@ column and top row (rounded to float32), and prunes a pair only when
 rho~ = C * inv_i * inv_j (inv = 1 / (sqrt(m) sigma), float32) exceeds the
 threshold by more than a guard band g.  Pruning is sound while
 |rho~ - rho| stays below g.  The band the library uses at each length is
-    g = max(1e-4, 2 * 2^-24 * sqrt(512) * gamma^2),
+    g = max(1.25e-4, 4 * 2^-24 * sqrt(512) * gamma^2),
 where gamma is the spread contrast of the series at that length: over blocks
 of 256 windows, the largest sigma of the two blocks on either side over the
 block's smallest sigma (windows with a small spread next to windows with a
@@ -35,7 +35,7 @@ import pytest
 
 from paper_2304_01660_amd import synth
 
-GUARD = 1e-4          # the library's default (smallest) guard band on rho
+GUARD = 1.25e-4       # the library's default (smallest) guard band on rho
 R = 512               # rows of the tallest sweep tile
 NCOLS = 512           # columns replayed per tile
 
@@ -56,7 +56,7 @@ def _helpers(T, m):
 
 def contrast_guard(sd):
     """The guard band for window sigmas `sd`: the spread contrast over blocks
-    of 256 windows, squared, times 2 * 2^-24 * sqrt(512), at least GUARD."""
+    of 256 windows, squared, times 4 * 2^-24 * sqrt(512), at least GUARD."""
     nb = (sd.shape[0] + 255) // 256
     pad = np.full(nb * 256, np.nan)
     pad[:sd.shape[0]] = sd
@@ -65,7 +65,7 @@ def contrast_guard(sd):
     bmin = np.nanmin(blk, axis=1)
     hi = np.array([bmax[max(0, q - 2):q + 3].max() for q in range(nb)])
     gam2 = float(np.max((hi / bmin) ** 2))
-    return max(GUARD, 2.0 * 2.0 ** -24 * math.sqrt(512.0) * gam2), gam2
+    return max(GUARD, 4.0 * 2.0 ** -24 * math.sqrt(512.0) * gam2), gam2
 
 
 def _zwin(T, m, mu, sd, lo, cnt):
