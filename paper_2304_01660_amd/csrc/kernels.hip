@@ -1814,144 +1814,184 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
 // so it runs on the FP64 matrix cores: V_MFMA_F64_16X16X4F64 multiplies a
 // 16 x 4 block of candidate values by a 4 x 16 block of the series, lane l
 // supplying X[l % 16][l / 16] and H[l / 16][l % 16] and receiving
-// D[l / 16 + 4 r][l % 16], r < 4.  A block owns POLISH_COLS consecutive
+// D[l / 16 + 4 r][l % 16], r < 4.  A block is POLISH_COLS consecutive
 // columns of one series (PM_CT tiles of 16 per wave) for one group of PM_G
 // candidates (grid.y); the columns' values and chunks of PM_KC offsets of
 // the candidates' centred windows are staged in LDS, so a lane reads one
 // value per matrix instruction (1024 FMAs).  One (max rho, argmax j)
-// partial per candidate.
+// partial per candidate and workgroup.
 constexpr int PM_WAVES = POLISH_COLS / 128;   // waves per block
 constexpr int PM_CT = 8;                      // 16-column tiles per wave
 constexpr int PM_G = 16;                      // candidates per block
-constexpr int PM_KC = 128;                    // window offsets per LDS chunk
+constexpr int PM_KC = 256;                    // window offsets per LDS chunk
+constexpr int PM_XS = PM_KC + 1;              // LDS row stride of a candidate window (odd: no bank conflicts)
+constexpr int PM_GRID = 512;                  // workgroups per candidate group (each sweeps blocks in turn)
+// A workgroup sweeps the column blocks g, g + G, ... of the flat block space
+// (all series, prefix table pfx); the candidates' windows stay in LDS while
+// consecutive blocks belong to the same series and the window fits one chunk.
 __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
-                                                          const int64_t* __restrict__ pfx)
+                                                          const int64_t* __restrict__ pfx,
+                                                          int64_t nblocks)
 {
     static_assert(PM_WAVES * PM_CT * 16 == POLISH_COLS, "polish block geometry");
     extern __shared__ double lds[];
     __shared__ double red_v[PM_WAVES][PM_G];
     __shared__ long long red_j[PM_WAVES][PM_G];
-    const int b = series_of(pfx, B, blockIdx.x);
-    const SeriesDev& s = S[b];
-    Ctrl* c = s.ctrl;
-    if (!c->active) return;
-    const int ncand = (int)c->ncand;
-    const int g0 = (int)blockIdx.y * PM_G;
-    if (g0 >= ncand) return;
-    const int32_t m = c->m;
-    const int64_t N = s.n - m + 1;
-    const double* __restrict__ mu = cur_mu(s, c);
-    const double* __restrict__ inv = s.inv64;  // 1/(sqrt(m) sigma), 0 for a flat window
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int ca = lane & 15, ka = lane >> 4;
-    const int64_t blk = blockIdx.x - pfx[b];
-    const int64_t j0 = blk * POLISH_COLS;
     const int colbase = w * 16 * PM_CT;
-    double* xg = lds;                   // [PM_G][PM_KC] candidate window chunk
-    double* ts = lds + PM_G * PM_KC;    // t[j0 .. j0 + POLISH_COLS + m + 4)
-    const int64_t stride = (int64_t)s.maxL + 8;
-    const double* __restrict__ xc = s.xc;
-    pm_acc_t acc[PM_CT];
-#pragma unroll
-    for (int ct = 0; ct < PM_CT; ++ct) acc[ct] = (pm_acc_t){0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < m; kb += PM_KC) {
-        const int kn = min(PM_KC, m - kb);
-        __syncthreads();  // the previous chunk is consumed
-        {
-            constexpr int PER = PM_G * PM_KC / (64 * PM_WAVES);
-            double v[PER];
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = tid + 64 * PM_WAVES * u;
-                const int g = e / PM_KC, k = e - g * PM_KC;
-                const int cid = min(g0 + g, ncand - 1);
-                v[u] = k < kn ? xc[cid * stride + kb + k] : 0.0;  // zero past m
-            }
-            // the columns' values travel together with the first chunk
-            if (kb == 0) lds_fill(ts, s.T + j0, POLISH_COLS + m + 4);
-#pragma unroll
-            for (int u = 0; u < PER; ++u) xg[tid + 64 * PM_WAVES * u] = v[u];
-        }
-        __syncthreads();
-        const double* xa = xg + ca * PM_KC + ka;
-        const double* tb = ts + colbase + kb + ka + ca;
-        for (int k4 = 0; k4 < kn; k4 += 4) {
-            const double av = xa[k4];
-#pragma unroll
-            for (int ct = 0; ct < PM_CT; ++ct)
-                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tb[k4 + 16 * ct], acc[ct], 0, 0, 0);
-        }
-    }
-    // epilogue: lane holds D[ka + 4 r][16 ct + ca]; rho = C inv_i inv_j
-    const double* __restrict__ sxs = xc + KP_MAX * stride;
-    int64_t ci[4];
-    double sxv[4], ivi[4], best[4];
+    const int g0 = (int)blockIdx.y * PM_G;
+    double* xg = lds;                   // [PM_G][PM_XS] candidate window chunk
+    double* ts = lds + PM_G * PM_XS;    // t[j0 .. j0 + POLISH_COLS + m + 4)
+    int loaded = -1;                    // series whose single-chunk windows are in xg
+    // running (max rho, smallest argmax j) of the lane's candidate rows over
+    // the blocks of series `cur` this workgroup has swept; the blocks of one
+    // series come in ascending order, so a strict > keeps the smaller j
+    int cur = -1;
+    int64_t cslot = 0;
+    double best[4];
     long long bj[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int cid = min(g0 + ka + 4 * r, ncand - 1);
-        ci[r] = s.cand[cid];
-        sxv[r] = sxs[cid];
-        ivi[r] = inv[ci[r]];
-        best[r] = -f_inf<double>();
-        bj[r] = 0x7fffffffffffffffll;
-    }
-    unsigned long long ev = 0;
-#pragma unroll
-    for (int ct = 0; ct < PM_CT; ++ct) {
-        const int64_t j = j0 + colbase + 16 * ct + ca;
-        if (j >= N) continue;
-        const double ivj = inv[j], muj = mu[j];
+    unsigned long long evb = 0;
+    // one partial per (candidate, workgroup): slot = the workgroup's first
+    // block of the series, which is below the grid size
+    auto flush = [&]() {
+        const SeriesDev& s = S[cur];
+        const int ncand = (int)s.ctrl->ncand;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (j <= ci[r] - m || j >= ci[r] + m) {
-                double rh;
-                if (ivi[r] == 0.0 || ivj == 0.0) {  // a flat window (R11)
-                    rh = (ivi[r] == 0.0 && ivj == 0.0) ? 1.0 : 0.0;
-                } else {
-                    const double Cv = acc[ct][r] - muj * sxv[r];
-                    rh = fmin(1.0, fmax(-1.0, Cv * ivi[r] * ivj));
-                }
-                if (rh > best[r]) {  // a lane's columns ascend with ct: ties keep the smaller j
-                    best[r] = rh;
-                    bj[r] = j;
-                }
-                if (g0 + ka + 4 * r < ncand) ++ev;
-            }
-        }
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+            for (int o = 8; o >= 1; o >>= 1) {  // the 16 lanes of one candidate row
+                const double v = __shfl_xor(best[r], o);
+                const long long jj = __shfl_xor(bj[r], o);
+                if (v > best[r] || (v == best[r] && jj < bj[r])) {
+                    best[r] = v;
+                    bj[r] = jj;
+                }
+            }
+            if (ca == 0) {
+                red_v[w][ka + 4 * r] = best[r];
+                red_j[w][ka + 4 * r] = bj[r];
+            }
+        }
+        __syncthreads();
+        if (tid < PM_G && g0 + tid < ncand) {
+            double bv = red_v[0][tid];
+            long long bjj = red_j[0][tid];
+            for (int q = 1; q < PM_WAVES; ++q)
+                if (red_v[q][tid] > bv || (red_v[q][tid] == bv && red_j[q][tid] < bjj)) {
+                    bv = red_v[q][tid];
+                    bjj = red_j[q][tid];
+                }
+            const int64_t slot = ((int64_t)(g0 + tid) * s.npart + cslot) * 2;
+            s.part[slot] = bv;
+            s.part[slot + 1] = (double)bjj;
+        }
+        const unsigned long long e = (unsigned long long)wave_sum((double)evb);
+        if (lane == 0 && e)
+            atomicAdd(&s.evc[EV_POL * EV_SLOTS + ((blockIdx.x + blockIdx.y + w) & (EV_SLOTS - 1))], e);
+        __syncthreads();  // red_v / red_j are free again
+        cur = -1;
+    };
+    for (int64_t fb = blockIdx.x; fb < nblocks; fb += gridDim.x) {
+        const int b = series_of(pfx, B, fb);
+        if (cur >= 0 && b != cur) flush();
+        const SeriesDev& s = S[b];
+        Ctrl* c = s.ctrl;
+        if (!c->active) continue;
+        const int ncand = (int)c->ncand;
+        if (g0 >= ncand) continue;
+        const int32_t m = c->m;
+        const int64_t N = s.n - m + 1;
+        const double* __restrict__ mu = cur_mu(s, c);
+        const double* __restrict__ inv = s.inv64;  // 1/(sqrt(m) sigma), 0 for a flat window
+        const int64_t blk = fb - pfx[b];
+        if (cur < 0) {
+            cur = b;
+            cslot = blk;
+            evb = 0;
 #pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) {  // the 16 lanes of one candidate row
-            const double v = __shfl_xor(best[r], o);
-            const long long jj = __shfl_xor(bj[r], o);
-            if (v > best[r] || (v == best[r] && jj < bj[r])) {
-                best[r] = v;
-                bj[r] = jj;
+            for (int r = 0; r < 4; ++r) {
+                best[r] = -f_inf<double>();
+                bj[r] = 0x7fffffffffffffffll;
             }
         }
-        if (ca == 0) {
-            red_v[w][ka + 4 * r] = best[r];
-            red_j[w][ka + 4 * r] = bj[r];
+        const int64_t j0 = blk * POLISH_COLS;
+        const int64_t stride = (int64_t)s.maxL + 8;
+        const double* __restrict__ xc = s.xc;
+        pm_acc_t acc[PM_CT];
+#pragma unroll
+        for (int ct = 0; ct < PM_CT; ++ct) acc[ct] = (pm_acc_t){0.0, 0.0, 0.0, 0.0};
+        const bool single = m <= PM_KC;
+        for (int kb = 0; kb < m; kb += PM_KC) {
+            const int kn = min(PM_KC, m - kb);
+            __syncthreads();  // the previous chunk and block are consumed
+            if (kb == 0) lds_fill(ts, s.T + j0, POLISH_COLS + m + 4);
+            if (!single || loaded != b) {
+                // eight loads in flight per thread before their stores
+                for (int e0 = 0; e0 < PM_G * PM_KC; e0 += 8 * 64 * PM_WAVES) {
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + tid + 64 * PM_WAVES * u;
+                        const int g = e / PM_KC, k = e - g * PM_KC;
+                        const int cid = min(g0 + g, ncand - 1);
+                        v[u] = k < kn ? xc[cid * stride + kb + k] : 0.0;  // zero past m
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + tid + 64 * PM_WAVES * u;
+                        const int g = e / PM_KC, k = e - g * PM_KC;
+                        xg[g * PM_XS + k] = v[u];
+                    }
+                }
+                loaded = single ? b : -1;
+            }
+            __syncthreads();
+            const double* xa = xg + ca * PM_XS + ka;
+            const double* tb = ts + colbase + kb + ka + ca;
+            for (int k4 = 0; k4 < kn; k4 += 4) {
+                const double av = xa[k4];
+#pragma unroll
+                for (int ct = 0; ct < PM_CT; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tb[k4 + 16 * ct], acc[ct], 0, 0, 0);
+            }
+        }
+        // epilogue: lane holds D[ka + 4 r][16 ct + ca]; rho = C inv_i inv_j
+        const double* __restrict__ sxs = xc + KP_MAX * stride;
+        int64_t ci[4];
+        double sxv[4], ivi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int cid = min(g0 + ka + 4 * r, ncand - 1);
+            ci[r] = s.cand[cid];
+            sxv[r] = sxs[cid];
+            ivi[r] = inv[ci[r]];
+        }
+#pragma unroll
+        for (int ct = 0; ct < PM_CT; ++ct) {
+            const int64_t j = j0 + colbase + 16 * ct + ca;
+            if (j >= N) continue;
+            const double ivj = inv[j], muj = mu[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (j <= ci[r] - m || j >= ci[r] + m) {
+                    double rh;
+                    if (ivi[r] == 0.0 || ivj == 0.0) {  // a flat window (R11)
+                        rh = (ivi[r] == 0.0 && ivj == 0.0) ? 1.0 : 0.0;
+                    } else {
+                        const double Cv = acc[ct][r] - muj * sxv[r];
+                        rh = fmin(1.0, fmax(-1.0, Cv * ivi[r] * ivj));
+                    }
+                    if (rh > best[r]) {  // a lane's columns ascend with ct and with the block
+                        best[r] = rh;
+                        bj[r] = j;
+                    }
+                    if (g0 + ka + 4 * r < ncand) ++evb;
+                }
+            }
         }
     }
-    __syncthreads();
-    if (tid < PM_G && g0 + tid < ncand) {
-        double bv = red_v[0][tid];
-        long long bjj = red_j[0][tid];
-        for (int q = 1; q < PM_WAVES; ++q)
-            if (red_v[q][tid] > bv || (red_v[q][tid] == bv && red_j[q][tid] < bjj)) {
-                bv = red_v[q][tid];
-                bjj = red_j[q][tid];
-            }
-        const int64_t slot = ((int64_t)(g0 + tid) * s.npart + blk) * 2;
-        s.part[slot] = bv;
-        s.part[slot + 1] = (double)bjj;
-    }
-    ev = (unsigned long long)wave_sum((double)ev);
-    if (lane == 0 && ev)
-        atomicAdd(&s.evc[EV_POL * EV_SLOTS + ((blockIdx.x + blockIdx.y + w) & (EV_SLOTS - 1))], ev);
+    if (cur >= 0) flush();
 }
 
 // Close the round of every series (one block each): reduce the polish
@@ -1959,7 +1999,8 @@ __global__ __launch_bounds__(64 * PM_WAVES) void k_polish(SeriesDev* S, int B,
 // length's top-k rows when the round found at least k range discords, and
 // lower MERLIN's r otherwise; count the series with work left in rem[0].
 constexpr int END_BLOCK = 1024;
-__global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* rem, int hot_rows)
+__global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* rem, int hot_rows,
+                                                          int npol)
 {
     __shared__ double nn_s[KP_MAX];
     __shared__ long long id_s[KP_MAX];
@@ -1980,9 +2021,10 @@ __global__ __launch_bounds__(END_BLOCK) void k_round_end(SeriesDev* S, int32_t* 
         // the block allows, at most a wave): strided partials loaded eight at
         // a time before they are compared (they come from other XCDs' caches,
         // so each batch costs a full memory latency), then a reduction over
-        // the tpc threads
+        // the tpc threads.  k_polish's npol workgroups left one partial each
+        // in the slots below min(blocks of this length, npol).
         const int64_t npart = s.npart;
-        const int64_t nblk = (s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS;
+        const int64_t nblk = std::min<int64_t>((s.n - m + 1 + POLISH_COLS - 1) / POLISH_COLS, npol);
         int tpc = 64;
         while (tpc > 1 && tpc * kp > END_BLOCK) tpc >>= 1;
         const int sub = tid & (tpc - 1);
@@ -2453,14 +2495,15 @@ hipError_t launch_round(const Batch& bt, const SweepCfg& cfg, const int64_t* tot
     default: launch_refine<2>(bt, cfg, total, st); break;
     }
     hipLaunchKernelGGL(k_select_top, dim3(bt.B), dim3(TOPK_BLOCK), 0, st, bt.s);
-    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_KC + POLISH_COLS + bt.maxL_all + 4);
+    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_XS + POLISH_COLS + bt.maxL_all + 4);
     cfg.timer->begin(3, st);
-    hipLaunchKernelGGL(k_polish,
-                       dim3((unsigned int)total[PFX_POLISH], (KP_MAX + PM_G - 1) / PM_G),
-                       dim3(64 * PM_WAVES), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH]);
+    const int npol = (int)std::min<int64_t>(total[PFX_POLISH], PM_GRID);
+    hipLaunchKernelGGL(k_polish, dim3((unsigned int)npol, (KP_MAX + PM_G - 1) / PM_G),
+                       dim3(64 * PM_WAVES), lds, st, bt.s, bt.B, bt.pfx[PFX_POLISH],
+                       total[PFX_POLISH]);
     cfg.timer->end(3, st);
     hipLaunchKernelGGL(k_round_end, dim3(bt.B), dim3(END_BLOCK), 0, st, bt.s, bt.remaining,
-                       64 * cfg.q_near);
+                       64 * cfg.q_near, npol);
     return hipGetLastError();
 }
 
@@ -2514,16 +2557,19 @@ hipError_t launch_stream_update(const Batch& bt, const SweepCfg& cfg, const int6
 hipError_t launch_stream_query(const Batch& bt, const int64_t* total, int32_t minL, int32_t maxL,
                                const unsigned long long* prof, int hot_rows, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_KC + POLISH_COLS + bt.maxL_all + 4);
+    const size_t lds = sizeof(double) * (size_t)(PM_G * PM_XS + POLISH_COLS + bt.maxL_all + 4);
+    const int npol = (int)std::min<int64_t>(total[PFX_POLISH], PM_GRID);
     for (int32_t m = minL; m <= maxL; ++m) {
         hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, st, bt.s, m, m == minL ? 2 : 1);
         hipLaunchKernelGGL(k_length, dim3((unsigned int)total[PFX_ELEM]), dim3(256), 0, st, bt.s, 1,
                            bt.pfx[PFX_ELEM]);
         hipLaunchKernelGGL(k_stream_query, dim3(256), dim3(256), 0, st, bt.s, prof);
         hipLaunchKernelGGL(k_select_top, dim3(1), dim3(TOPK_BLOCK), 0, st, bt.s);
-        hipLaunchKernelGGL(k_polish, dim3((unsigned int)total[PFX_POLISH], (KP_MAX + PM_G - 1) / PM_G),
-                           dim3(64 * PM_WAVES), lds, st, bt.s, 1, bt.pfx[PFX_POLISH]);
-        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(END_BLOCK), 0, st, bt.s, bt.remaining, hot_rows);
+        hipLaunchKernelGGL(k_polish, dim3((unsigned int)npol, (KP_MAX + PM_G - 1) / PM_G),
+                           dim3(64 * PM_WAVES), lds, st, bt.s, 1, bt.pfx[PFX_POLISH],
+                           total[PFX_POLISH]);
+        hipLaunchKernelGGL(k_round_end, dim3(1), dim3(END_BLOCK), 0, st, bt.s, bt.remaining, hot_rows,
+                           npol);
     }
     return hipGetLastError();
 }
