@@ -48,8 +48,9 @@ KERNEL_NAMES = {
     "refine": "k_refine",
     "polish": "k_polish",
     "length": "k_length",
+    "select_band": "k_select_band",
 }
-CLASS_NAMES = ("select_near", "select_far", "refine", "polish", "length")
+CLASS_NAMES = ("select_near", "select_far", "refine", "polish", "length", "select_band")
 SERIES_TEXT = {
     "c2": "seeded random walk with 5 injected sine bursts/level shifts (seed 1)",
     "c3": ("seeded ECG-like beat train (3 Gaussian bumps per beat, period U(240, 260), "
@@ -232,7 +233,8 @@ def search_leg(api, torch, dev, w, tuned, steps, warmup):
             "evals_per_step": agg["kernel_evals"][ci] / steps,
             "avg_launch_us": (ms / launches * 1e3) if launches else None,
         }
-    dom = max(("select_near", "select_far", "refine"), key=lambda k: kernels[k]["ms_per_step"])
+    dom = max(("select_near", "select_far", "refine", "select_band"),
+              key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
     achieved = None
     if dk["ms_per_step"] > 0:

@@ -82,7 +82,11 @@ typedef struct {
     int32_t rows_far;      /* row-tile height of the split selection pass; 0 = as near. */
     int32_t rows_refine;   /* row-tile height of the refinement pass; 0 = 128. */
     int32_t far_grid;      /* workgroups of the split passes (1..65536); 0 = 2048. */
-    int32_t reserved[3];   /* must be zero */
+    int32_t band_pass;     /* 1: before the first selection pass, test every
+                              subsequence against its 256 nearest non-self offsets
+                              on the right, swept down the diagonals (prunes only;
+                              results unchanged); 0 or -1: off. */
+    int32_t reserved[2];   /* must be zero */
 } palmad_options;
 
 /* Record HIP events around the sweep kernels and report their summed device
@@ -100,7 +104,8 @@ enum {
     PALMAD_KERNEL_REFINE = 2,      /* refinement pass (exact FP64 nearest neighbour) */
     PALMAD_KERNEL_POLISH = 3,      /* direct FP64 distances of the top candidates */
     PALMAD_KERNEL_LENGTH = 4,      /* per-length statistics, helpers and round resets */
-    PALMAD_KERNEL_CLASSES = 5
+    PALMAD_KERNEL_SELECT_BAND = 5, /* diagonal band pre-pass of the first selection pass */
+    PALMAD_KERNEL_CLASSES = 6
 };
 
 /* Per-call counters (host struct, filled when the call returns). */

@@ -38,8 +38,13 @@ class Options(ctypes.Structure):
         ("rows_far", ctypes.c_int32),
         ("rows_refine", ctypes.c_int32),
         ("far_grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("band_pass", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
+
+
+# PALMAD_KERNEL_CLASSES: near, far, refine, polish, length, band
+KERNEL_CLASSES = 6
 
 
 class Stats(ctypes.Structure):
@@ -50,9 +55,9 @@ class Stats(ctypes.Structure):
         ("range_searches", ctypes.c_uint64),
         ("survivors", ctypes.c_uint64),
         ("seconds", ctypes.c_double),
-        ("kernel_evals", ctypes.c_uint64 * 5),
-        ("kernel_launches", ctypes.c_uint64 * 5),
-        ("kernel_ms", ctypes.c_double * 5),
+        ("kernel_evals", ctypes.c_uint64 * KERNEL_CLASSES),
+        ("kernel_launches", ctypes.c_uint64 * KERNEL_CLASSES),
+        ("kernel_ms", ctypes.c_double * KERNEL_CLASSES),
         ("rows_after_near", ctypes.c_uint64),
         ("rows_after_far", ctypes.c_uint64),
     ]
@@ -174,9 +179,11 @@ def check(rc: int, ctx=None):
 
 
 def make_options(dist_bits=0, guard=0.0, near_cols=0, chunk_cols=0, time_kernels=False,
-                 rows_near=0, rows_far=0, rows_refine=0, far_grid=0, graphs=True) -> Options:
+                 rows_near=0, rows_far=0, rows_refine=0, far_grid=0, graphs=True,
+                 band_pass=0) -> Options:
     o = Options()
     o.far_grid = int(far_grid)
+    o.band_pass = int(band_pass)
     o.rows_near = int(rows_near)
     o.rows_far = int(rows_far)
     o.rows_refine = int(rows_refine)

@@ -61,7 +61,8 @@ def _workspace(nbytes: int, dev) -> torch.Tensor:
 def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
              guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0, workspace=None,
              return_stats: bool = False, time_kernels: bool = False, rows_near: int = 0,
-             rows_far: int = 0, rows_refine: int = 0, far_grid: int = 0, graphs: bool = True):
+             rows_far: int = 0, rows_refine: int = 0, far_grid: int = 0, graphs: bool = True,
+             band_pass: int = 0):
     """Top-k discords of every length in [minL, maxL].
 
     Returns a dict of device tensors: idx int64[L*k], len int32[L*k],
@@ -73,7 +74,7 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
     n = T.shape[0]
     L = maxL - minL + 1
     o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
-                          rows_far, rows_refine, far_grid, graphs)
+                          rows_far, rows_refine, far_grid, graphs, band_pass)
     nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
                             near_cols=near_cols, chunk_cols=chunk_cols)
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
@@ -103,7 +104,8 @@ def discords(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 
 def discord_heatmap(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits: int = 0,
                     guard: float = 0.0, near_cols: int = 0, chunk_cols: int = 0,
                     return_stats: bool = False, rows_near: int = 0, rows_far: int = 0,
-                    rows_refine: int = 0, far_grid: int = 0, graphs: bool = True):
+                    rows_refine: int = 0, far_grid: int = 0, graphs: bool = True,
+                    band_pass: int = 0):
     """Top-k discords of every length plus the discord heatmap (Eq. (11)).
 
     Returns the dict of ``discords`` plus ``heat`` float64[L, n - minL + 1]
@@ -117,7 +119,7 @@ def discord_heatmap(T: torch.Tensor, minL: int, maxL: int, k: int, *, dist_bits:
     L = maxL - minL + 1
     ld = n - minL + 1
     o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, False, rows_near, rows_far,
-                          rows_refine, far_grid, graphs)
+                          rows_refine, far_grid, graphs, band_pass)
     nbytes = workspace_size(n, minL, maxL, k, dist_bits=dist_bits, guard=guard,
                             near_cols=near_cols, chunk_cols=chunk_cols)
     ws = _workspace(nbytes, dev)
@@ -191,6 +193,7 @@ def discords_batched(series, minL, maxL, k: int, *, dist_bits: int = 0, guard: f
                      near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False,
                      time_kernels: bool = False, rows_near: int = 0, rows_far: int = 0,
                      rows_refine: int = 0, far_grid: int = 0, graphs: bool = True,
+                     band_pass: int = 0,
                      workspace=None):
     """Top-k discords of every length of several series in one search.
 
@@ -223,7 +226,7 @@ def discords_batched(series, minL, maxL, k: int, *, dist_bits: int = 0, guard: f
     c_lo = (ctypes.c_int32 * B)(*lo)
     c_hi = (ctypes.c_int32 * B)(*hi)
     o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
-                          rows_far, rows_refine, far_grid, graphs)
+                          rows_far, rows_refine, far_grid, graphs, band_pass)
     nbytes = ctypes.c_size_t(0)
     _lib.check(_lib.lib().palmad_batched_workspace_size(B, offs, c_lo, c_hi, int(k),
                                                         ctypes.byref(o), ctypes.byref(nbytes)))
@@ -261,7 +264,7 @@ def discords_batched(series, minL, maxL, k: int, *, dist_bits: int = 0, guard: f
 
 
 TUNED_KEYS = ("dist_bits", "guard", "near_cols", "chunk_cols", "rows_near", "rows_far",
-              "rows_refine", "far_grid")
+              "rows_refine", "far_grid", "band_pass")
 
 
 def autotune(series, minL, maxL, k: int, *, probe_lengths: int = 6, reps: int = 2, **base):
@@ -307,7 +310,7 @@ def autotune(series, minL, maxL, k: int, *, probe_lengths: int = 6, reps: int = 
 def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, guard: float = 0.0,
                    near_cols: int = 0, chunk_cols: int = 0, return_stats: bool = False,
                    time_kernels: bool = False, rows_near: int = 0, rows_far: int = 0,
-                   rows_refine: int = 0, far_grid: int = 0):
+                   rows_refine: int = 0, far_grid: int = 0, band_pass: int = 0):
     """All subsequences of length m whose nearest non-self match is >= r away.
 
     Returns (mask bool[N] on the device, nn_dist float64[N] valid where mask,
@@ -318,7 +321,7 @@ def range_discords(T: torch.Tensor, m: int, r: float, *, dist_bits: int = 0, gua
     n = T.shape[0]
     N = n - m + 1
     o = _lib.make_options(dist_bits, guard, near_cols, chunk_cols, time_kernels, rows_near,
-                          rows_far, rows_refine, far_grid)
+                          rows_far, rows_refine, far_grid, True, band_pass)
     nbytes = workspace_size(n, m, m, 1, dist_bits=dist_bits, guard=guard, near_cols=near_cols,
                             chunk_cols=chunk_cols)
     ws = _workspace(nbytes, dev)

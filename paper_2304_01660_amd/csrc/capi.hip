@@ -83,13 +83,14 @@ struct Opts {
     unsigned int flags;
     int rows_near, rows_far, rows_refine;
     int far_grid;
+    int band_pass;
 };
 
 constexpr unsigned int KNOWN_FLAGS = PALMAD_FLAG_TIME_KERNELS | PALMAD_FLAG_NO_GRAPH;
 
 int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
 {
-    Opts r = {32, 1.25e-4f, 2048, 1024, 0u, 0, 0, 0, 2048};
+    Opts r = {32, 1.25e-4f, 2048, 1024, 0u, 0, 0, 0, 2048, 0};
     if (o) {
         if (o->flags & ~KNOWN_FLAGS)
             return fail(ctx, PALMAD_EINVAL, "unknown option flags 0x%x", o->flags);
@@ -105,8 +106,11 @@ int read_opts(palmad_ctx* ctx, const palmad_options* o, Opts* out)
         if (o->far_grid < 0 || o->far_grid > 65536)
             return fail(ctx, PALMAD_EINVAL, "far_grid must be in [0, 65536] (got %d)", o->far_grid);
         if (o->far_grid > 0) r.far_grid = o->far_grid;
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 2; ++i)
             if (o->reserved[i] != 0) return fail(ctx, PALMAD_EINVAL, "options.reserved must be zero");
+        if (o->band_pass < -1 || o->band_pass > 1)
+            return fail(ctx, PALMAD_EINVAL, "band_pass must be -1, 0 or 1 (got %d)", o->band_pass);
+        r.band_pass = o->band_pass == 1 ? 1 : 0;
         if (o->dist_bits != 0) {
             if (o->dist_bits != 32 && o->dist_bits != 64)
                 return fail(ctx, PALMAD_EINVAL, "dist_bits must be 0, 32 or 64 (got %d)",
@@ -185,6 +189,7 @@ SweepCfg cfg_of(const Opts& o, const KernelTimer* timer)
     c.q_far = far_rows / 64;
     c.q_ref = ref_rows / 64;
     c.max_attempts = MAX_ATTEMPTS;
+    c.band = o.band_pass;
     c.timer = timer;
     return c;
 }
@@ -389,10 +394,10 @@ int prepare(palmad_ctx* ctx, const Batch& bt, const Plan& p)
 std::string graph_key(const Batch& bt, const SweepCfg& c, const Plan& p)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "%p|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%a|%d|", (void*)bt.s, bt.B,
+    snprintf(buf, sizeof buf, "%p|%d|%d|%lld|%d|%d|%d|%d|%d|%d|%d|%a|%d|%d|", (void*)bt.s, bt.B,
              bt.maxL_all, (long long)bt.Nmax_all,
              c.near_cols, c.chunk_cols, c.dist_bits, c.far_grid, c.q_near, c.q_far, c.q_ref,
-             (double)c.guard, c.max_attempts);
+             (double)c.guard, c.max_attempts, c.band);
     std::string k = buf;
     for (int q = 0; q < PFX_KINDS; ++q) k += std::to_string(p.totals[q]) + ",";
     return k;
@@ -458,7 +463,7 @@ int gather_stats(palmad_ctx* ctx, const Batch& bt, const KernelTimer& t, double 
     if (!stats) return PALMAD_OK;
     HIP_TRY(launch_sum_stats(bt, bt.sums, ctx->work));
     unsigned long long* h = (unsigned long long*)(ctx->pinned + 16);
-    HIP_TRY(hipMemcpyAsync(h, bt.sums, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(h, bt.sums, 10 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            ctx->work));
     HIP_TRY(hipStreamSynchronize(ctx->work));
     std::memset(stats, 0, sizeof *stats);
@@ -471,6 +476,7 @@ int gather_stats(palmad_ctx* ctx, const Batch& bt, const KernelTimer& t, double 
     stats->kernel_evals[PALMAD_KERNEL_SELECT_FAR] = h[6];
     stats->kernel_evals[PALMAD_KERNEL_REFINE] = h[1];
     stats->kernel_evals[PALMAD_KERNEL_POLISH] = h[2];
+    stats->kernel_evals[PALMAD_KERNEL_SELECT_BAND] = h[9];
     stats->rows_after_near = h[7];
     stats->rows_after_far = h[8];
     stats->seconds = secs;

@@ -36,9 +36,9 @@ constexpr int HOT_FRAC = 8;
 
 // Pair-evaluation counters: EV_SLOTS slots per class, so that the many
 // work items of a launch add to different addresses.
-constexpr int EV_CLASSES = 4;  // first selection pass, split pass, refinement, exact pass
+constexpr int EV_CLASSES = 5;  // first selection pass, split pass, refinement, exact pass, band pre-pass
 constexpr int EV_SLOTS = 64;
-enum { EV_NEAR = 0, EV_FAR = 1, EV_REF = 2, EV_POL = 3 };
+enum { EV_NEAR = 0, EV_FAR = 1, EV_REF = 2, EV_POL = 3, EV_BAND = 4 };
 
 // Device-resident control block of one series (the MERLIN state of Alg. 1
 // plus the work counters of the current round).  Fields that work items
@@ -147,7 +147,8 @@ enum PrefixKind {
     PFX_NEAR,       // first-pass selection items: tiles x chunks
     PFX_TSEL,       // blocks of 256 over selection tiles (compaction)
     PFX_TREF,       // blocks of 256 over refinement tiles (compaction)
-    PFX_POLISH,     // blocks of 256 columns (polish)
+    PFX_POLISH,     // blocks of POLISH_COLS columns (polish)
+    PFX_BAND,       // row segments of the diagonal band pre-pass
     PFX_KINDS
 };
 
@@ -162,7 +163,7 @@ struct Batch {
 };
 
 // Optional per-kernel event timing (host side).
-constexpr int KCLASSES = 5;  // select near, select far, refine, polish, per-length statistics
+constexpr int KCLASSES = 6;  // select near, select far, refine, polish, per-length statistics, band
 struct KernelTimer {
     bool on;
     hipEvent_t ev[KCLASSES][2];
@@ -186,6 +187,7 @@ struct SweepCfg {
     int far_grid;              // workgroups of the queued passes
     int q_near, q_far, q_ref;  // rows per lane of each pass's tiles (2, 4 or 8)
     int max_attempts;          // range searches allowed per length (MAX_ATTEMPTS)
+    int band;                  // 1: diagonal band pre-pass before the first selection pass
     const KernelTimer* timer;
 };
 

@@ -1306,6 +1306,239 @@ __device__ __forceinline__ unsigned long long first_item(unsigned long long cum)
     return ((unsigned long long)blockIdx.x + G - cum % G) % G;
 }
 
+// ----- diagonal band pre-pass of the first selection pass -----
+// The pairs (i, i + d), d in [m, m + BAND_D), of every subsequence — its
+// nearest non-self matches on the right — swept down the diagonals.  A work
+// item is one wavefront owning BAND_D consecutive diagonals (BAND_Q per
+// lane, consecutive) over BAND_S consecutive rows.  Each lane carries its
+// diagonals' values from row to row with the centred recurrence (R23) in
+// the selection precision, started from exact FP64 values of the item's top
+// row (one Hankel tile on the matrix cores), so every value is at most
+// BAND_S steps from an exact one, as in the row-tile sweeps.  A pair that
+// passes the selection test kills both subsequences: the row through the
+// wave's ballot of the step, the column through per-lane bit histories
+// (one add-with-carry per pair) merged in LDS and published once per item.
+// No tile straddles the exclusion zone, so every pair evaluated counts.
+// The pass only prunes: the row-tile passes after it still sweep each tile
+// with a live row from its first non-self column, which keeps the recorded
+// right-side maxima of the surviving rows complete.
+constexpr int BAND_Q = 4;
+constexpr int BAND_D = 64 * BAND_Q;      // diagonals per item
+constexpr int BAND_S = 256;              // rows per item (a multiple of 64)
+constexpr int BAND_C = BAND_S + BAND_D;  // column records per item (the last one is padding)
+constexpr int BAND_W32 = (BAND_C + 64) / 32;  // column-kill words, aligned to the bitmap
+static_assert(BAND_D == BCOLS, "one Hankel tile gives the top row's values");
+
+__host__ __device__ constexpr size_t band_lds_bytes(int m, int fbytes)
+{
+    // phase 1: top-row window + skewed series stretch for the Hankel tile
+    // phase 2: column records, row records, column-kill bits
+    return (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(BCOLS + m + 16 - 1) + 1 + 3) & ~3)) >
+                   (size_t)4 * fbytes * (BAND_C + BAND_S) + 4 * BAND_W32
+               ? (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(BCOLS + m + 16 - 1) + 1 + 3) & ~3))
+               : (size_t)4 * fbytes * (BAND_C + BAND_S) + 4 * BAND_W32;
+}
+
+// One row step's kill tests, for the BAND_Q pairs of every lane: per slot
+// km = 2 km + (mg > 0) (the lane's column history, newest step in bit 0) as
+// one compare and one add-with-carry, and the row's history rh = 2 rh +
+// (some pair of the wave has mg > 0) in scalar instructions.  (Written as C,
+// the compiler reassociates the unrolled histories into sums of selected
+// powers of two and keeps every step's masks alive until the end.)
+#define BAND_CMP_F32 "v_cmp_lt_f32_e64"
+#define BAND_CMP_F64 "v_cmp_lt_f64_e64"
+#define BAND_HIT_ASM(CMP)                                                                   \
+    CMP " %[m0], 0, %[g0]\n\t"                                                              \
+        "v_addc_co_u32_e64 %[k0], %[co], %[k0], %[k0], %[m0]\n\t" CMP " %[m1], 0, %[g1]\n\t" \
+        "v_addc_co_u32_e64 %[k1], %[co], %[k1], %[k1], %[m1]\n\t" CMP " %[m2], 0, %[g2]\n\t" \
+        "v_addc_co_u32_e64 %[k2], %[co], %[k2], %[k2], %[m2]\n\t" CMP " %[m3], 0, %[g3]\n\t" \
+        "v_addc_co_u32_e64 %[k3], %[co], %[k3], %[k3], %[m3]\n\t"                           \
+        "s_or_b64 %[m0], %[m0], %[m1]\n\t"                                                   \
+        "s_or_b64 %[m2], %[m2], %[m3]\n\t"                                                   \
+        "s_or_b64 %[m0], %[m0], %[m2]\n\t"                                                   \
+        "s_cmp_lg_u64 %[m0], 0\n\t"                                                          \
+        "s_addc_u32 %[rh], %[rh], %[rh]"
+template <typename F>
+__device__ __forceinline__ void band_hits(const F (&mg)[BAND_Q], unsigned int (&km)[BAND_Q],
+                                          unsigned int& rh)
+{
+    static_assert(BAND_Q == 4, "four slots per lane");
+    unsigned long long m0, m1, m2, m3, co;
+    if constexpr (sizeof(F) == 4) {
+        asm(BAND_HIT_ASM(BAND_CMP_F32)
+            : [k0] "+v"(km[0]), [k1] "+v"(km[1]), [k2] "+v"(km[2]), [k3] "+v"(km[3]),
+              [rh] "+s"(rh), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3),
+              [co] "=&s"(co)
+            : [g0] "v"(mg[0]), [g1] "v"(mg[1]), [g2] "v"(mg[2]), [g3] "v"(mg[3])
+            : "scc");
+    } else {
+        asm(BAND_HIT_ASM(BAND_CMP_F64)
+            : [k0] "+v"(km[0]), [k1] "+v"(km[1]), [k2] "+v"(km[2]), [k3] "+v"(km[3]),
+              [rh] "+s"(rh), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3),
+              [co] "=&s"(co)
+            : [g0] "v"(mg[0]), [g1] "v"(mg[1]), [g2] "v"(mg[2]), [g3] "v"(mg[3])
+            : "scc");
+    }
+}
+
+template <typename F>
+__global__ __launch_bounds__(64) void k_select_band(SeriesDev* S, int B, const int64_t* __restrict__ pfx)
+{
+    extern __shared__ double lds[];
+    const int b = series_of(pfx, B, blockIdx.x);
+    const SeriesDev& s = S[b];
+    Ctrl* c = s.ctrl;
+    if (!c->active || !c->prune) return;
+    const SweepArgs<F> A = args_of<F>(s, c);
+    const int32_t m = A.m;
+    const int64_t i0 = (int64_t)(blockIdx.x - pfx[b]) * BAND_S;
+    const int64_t j0 = i0 + m;  // column of the top row on the first diagonal
+    // every column of the item inside the series (the tail is left to the
+    // row-tile passes)
+    if (j0 + BAND_C - 1 > A.N) return;
+    const int lane = threadIdx.x;
+    const F thr = sel_threshold<F>(c);
+
+    // exact top-row values C(i0, j0 + p), p < 256
+    F C[BAND_Q];
+    {
+        double* xp = lds;
+        double* ws = lds + hk_vp_doubles(m);
+        const double mui0 = A.mu[i0];
+        const int nvp = hk_vp_doubles(m);
+        double sx = 0.0;
+        for (int t = lane; t < nvp; t += 64) {
+            const int k = t - HK_PAD;
+            double v = 0.0;
+            if (k >= 0 && k < m) {
+                v = A.T[i0 + k] - mui0;
+                sx += v;
+            }
+            xp[t] = v;
+        }
+        const double Sx = wave_sum(sx);
+        stage_skewed(ws, A.T + j0, BCOLS + m + 16);
+        __syncthreads();
+        const pm_acc_t D = hankel16(xp, ws, 0, m);
+        __syncthreads();  // the stretch is consumed: its space takes the values
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = hk_offset(q);
+            ws[p] = D[q] - A.mu[j0 + p] * Sx;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BAND_Q; ++q) C[q] = (F)ws[BAND_Q * lane + q];
+        __syncthreads();  // phase 1 is over
+    }
+
+    // column records (helpers of column j0 + e: df[j-1], dg[j-1], inv[j])
+    // and row records (df[i-1], dg[i-1], -thr / inv_i: the margin offset)
+    H4<F>* colh = (H4<F>*)lds;
+    H4<F>* rowh = colh + BAND_C;
+    uint32_t* kb = (uint32_t*)(rowh + BAND_S);
+    {
+        constexpr int NE = BAND_C / 64, NT = BAND_S / 64;
+        F v[NE][3];
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int64_t j = j0 + lane + 64 * u;
+            v[u][0] = A.df[j - 1];
+            v[u][1] = A.dg[j - 1];
+            v[u][2] = A.inv[j];
+        }
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            H4<F> h;
+            h.df = v[u][0];
+            h.dg = v[u][1];
+            h.inv = v[u][2];
+            h.B = F(0);
+            colh[lane + 64 * u] = h;
+        }
+        F r[NT][3];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int t = lane + 64 * u;
+            const int64_t ip = i0 + t - (t > 0 ? 1 : 0);  // row 0 takes no step
+            r[u][0] = A.df[ip];
+            r[u][1] = A.dg[ip];
+            r[u][2] = A.inv[i0 + t];
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            H4<F> h;
+            h.df = r[u][0];
+            h.dg = r[u][1];
+            h.inv = r[u][2] > F(0) ? -(thr / r[u][2]) : -f_inf<F>();
+            h.B = F(0);
+            rowh[lane + 64 * u] = h;
+        }
+        if (lane < BAND_W32) kb[lane] = 0u;
+    }
+    __syncthreads();
+
+    // row i0 + t, slot q of the lane: diagonal m + BAND_Q lane + q, column
+    // record t + BAND_Q lane + q, held in hv[(q + t) % BAND_Q] (the records
+    // shift down one slot per row; the top slot is read from LDS)
+    const int off = (int)(j0 & 63);
+    H4<F> hv[BAND_Q];
+#pragma unroll
+    for (int q = 0; q < BAND_Q; ++q) hv[q] = colh[BAND_Q * lane + q];
+    unsigned int km[BAND_Q];
+#pragma unroll
+    for (int q = 0; q < BAND_Q; ++q) km[q] = 0u;
+    unsigned long long rowbits = 0ull;
+    unsigned int rhist = 0u;
+    for (int t0 = 0; t0 < BAND_S; t0 += 32) {
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int t = t0 + u;
+            const H4<F> rh = rowh[t];
+            if (u != 0 || t0 != 0) {
+                hv[(BAND_Q - 1 + u) % BAND_Q] = colh[t + BAND_Q * lane + BAND_Q - 1];
+#pragma unroll
+                for (int q = 0; q < BAND_Q; ++q) {
+                    const H4<F>& h = hv[(q + u) % BAND_Q];
+                    C[q] = f_fma(rh.df, h.dg, f_fma(h.df, rh.dg, C[q]));
+                }
+            }
+            F mg[BAND_Q];
+#pragma unroll
+            for (int q = 0; q < BAND_Q; ++q) mg[q] = f_fma(C[q], hv[(q + u) % BAND_Q].inv, rh.inv);
+            band_hits<F>(mg, km, rhist);
+        }
+        // bit 31 - u of rhist: row i0 + t0 + u; of km[q]: column record
+        // t0 + u + BAND_Q lane + q
+        rowbits |= (unsigned long long)__builtin_bitreverse32(rhist) << (t0 & 32);
+        rhist = 0u;
+#pragma unroll
+        for (int q = 0; q < BAND_Q; ++q) {
+            const unsigned int v = __builtin_bitreverse32(km[q]);
+            if (v) {
+                const int cb = off + t0 + BAND_Q * lane + q;
+                atomicOr(&kb[cb >> 5], v << (cb & 31));
+                if (cb & 31) atomicOr(&kb[(cb >> 5) + 1], v >> (32 - (cb & 31)));
+            }
+            km[q] = 0u;
+        }
+        if ((t0 & 63) == 32) {
+            if (lane == 0 && rowbits) atomicAnd(&A.alive[(i0 + t0 - 32) >> 6], ~rowbits);
+            rowbits = 0ull;
+        }
+    }
+    __syncthreads();
+    // the killed columns, one bitmap word per lane (kb bit off + e: column j0 + e)
+    if (lane < BAND_W32 / 2) {
+        const unsigned long long bits =
+            (unsigned long long)kb[2 * lane] | ((unsigned long long)kb[2 * lane + 1] << 32);
+        if (bits) atomicAnd(&A.alive[(j0 >> 6) + lane], ~bits);
+    }
+    if (lane == 0)
+        atomicAdd(&s.evc[EV_BAND * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))],
+                  (unsigned long long)BAND_S * BAND_D);
+}
+
 // First selection pass: every row tile's nearest near_cols columns, split
 // into chunks of `chunk` columns that run concurrently; each stops as soon
 // as the whole tile is dead.
@@ -2458,6 +2691,15 @@ template <typename F>
 static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* total,
                           hipStream_t st)
 {
+    if (cfg.band && total[PFX_BAND] > 0) {
+        cfg.timer->begin(5, st);
+        hipLaunchKernelGGL((k_select_band<F>), dim3((unsigned int)total[PFX_BAND]), dim3(64),
+                           band_lds_bytes(bt.maxL_all, (int)sizeof(F)), st, bt.s, bt.B, bt.pfx[PFX_BAND]);
+        cfg.timer->end(5, st);
+    } else {
+        cfg.timer->begin(5, st);
+        cfg.timer->end(5, st);
+    }
     switch (cfg.q_near) {
     case 2: launch_near<F, 2>(bt, cfg, total, st); break;
     case 4: launch_near<F, 4>(bt, cfg, total, st); break;
@@ -2636,11 +2878,11 @@ hipError_t launch_stats_to(const Batch& bt, int32_t minL, int32_t m, const int64
 
 // Sum of the per-series counters of a call (one block):
 // out = {evals_sel, evals_ref, evals_pol, rounds, survivors, evals_near, evals_far,
-//        rows_near, rows_far}.
+//        rows_near, rows_far, evals_band}.
 __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
 {
-    __shared__ unsigned long long acc[9];
-    if (threadIdx.x < 9) acc[threadIdx.x] = 0ull;
+    __shared__ unsigned long long acc[10];
+    if (threadIdx.x < 10) acc[threadIdx.x] = 0ull;
     __syncthreads();
     for (int b = 0; b < B; ++b) {
         const SeriesDev& s = S[b];
@@ -2648,8 +2890,13 @@ __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
             const unsigned long long v = s.evc[e];
             const int cls = e / EV_SLOTS;
             if (v) {
-                if (cls == EV_NEAR || cls == EV_FAR) atomicAdd(&acc[0], v);
-                atomicAdd(&acc[cls == EV_NEAR ? 5 : cls == EV_FAR ? 6 : cls == EV_REF ? 1 : 2], v);
+                if (cls == EV_NEAR || cls == EV_FAR || cls == EV_BAND) atomicAdd(&acc[0], v);
+                atomicAdd(&acc[cls == EV_NEAR  ? 5
+                               : cls == EV_FAR ? 6
+                               : cls == EV_REF ? 1
+                               : cls == EV_POL ? 2
+                                               : 9],
+                          v);
             }
         }
         if (threadIdx.x == 0) {
@@ -2661,7 +2908,7 @@ __global__ void k_sum_stats(SeriesDev* S, int B, unsigned long long* out)
         }
         __syncthreads();
     }
-    if (threadIdx.x < 9) out[threadIdx.x] = acc[threadIdx.x];
+    if (threadIdx.x < 10) out[threadIdx.x] = acc[threadIdx.x];
 }
 
 hipError_t launch_sum_stats(const Batch& bt, unsigned long long* out, hipStream_t st)
@@ -2924,6 +3171,7 @@ void series_blocks(const Layout& l, const SweepCfg& cfg, int64_t out[PFX_KINDS])
     out[PFX_TSEL] = ((l.Nmax + rf - 1) / rf + 255) / 256;
     out[PFX_TREF] = ((l.Nmax + rr - 1) / rr + 255) / 256;
     out[PFX_POLISH] = l.npart;
+    out[PFX_BAND] = (l.Nmax + BAND_S - 1) / BAND_S;
 }
 
 }  // namespace palmad

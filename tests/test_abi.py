@@ -71,9 +71,13 @@ def test_options_validation():
     rc, _ = _ws(1000, 10, 20, 1, rows_near=128, rows_far=256, rows_refine=512)
     assert rc == 0
     o = _lib.make_options()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     b = ctypes.c_size_t(0)
     assert _lib.lib().palmad_workspace_size(1000, 10, 20, 1, ctypes.byref(o), ctypes.byref(b)) == -1
+    rc, _ = _ws(1000, 10, 20, 1, band_pass=2)
+    assert rc == -1
+    rc, _ = _ws(1000, 10, 20, 1, band_pass=1)
+    assert rc == 0
 
 
 def test_null_pointer_arguments_are_rejected():
