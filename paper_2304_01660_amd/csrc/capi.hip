@@ -1135,16 +1135,18 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
     int evaluated = 1;
     static const int rows_v[] = {128, 256, 512};
     static const int chunk_v[] = {256, 512, 1024, 2048};
-    static const int near_v[] = {2048, 8192, 32768, 1 << 30};
+    static const int near_v[] = {1024, 2048, 8192, 32768, 1 << 30};
     static const int grid_v[] = {2048, 3072, 4096, 6144, 8192};
+    static const int band_v[] = {0, 1};
     struct Axis {
         int* field;
         const int* vals;
         int count;
     };
     const Axis axes[] = {
-        {&cur.chunk_cols, chunk_v, 4}, {&cur.near_cols, near_v, 4},  {&cur.rows_near, rows_v, 3},
+        {&cur.chunk_cols, chunk_v, 4}, {&cur.near_cols, near_v, 5},  {&cur.rows_near, rows_v, 3},
         {&cur.rows_far, rows_v, 3},    {&cur.rows_refine, rows_v, 3}, {&cur.far_grid, grid_v, 5},
+        {&cur.band_pass, band_v, 2},
     };
     // coordinate search, two passes over the axes (the best chunk length and
     // first-pass width depend on the tile heights chosen after them)
@@ -1180,6 +1182,7 @@ int palmad_autotune(palmad_ctx* ctx, const double* values, const int64_t* offset
     r.rows_far = cur.rows_far;
     r.rows_refine = cur.rows_refine;
     r.far_grid = cur.far_grid;
+    r.band_pass = cur.band_pass;
     *best = r;
     if (report) {
         report->evaluated = evaluated;

@@ -1,7 +1,8 @@
 """Stored tile geometry, chosen by the autotuner, keyed by problem size.
 
 The sweeps' tile geometry (row-tile heights, first-pass width, chunk
-length, queued-pass grid) changes only the order of floating-point work,
+length, queued-pass grid, and whether the diagonal band pre-pass runs)
+changes only the order of floating-point work,
 never the result beyond the documented tolerance, but it decides how well
 a problem fills the GPU.  The stored table (``tuned_gfx950.json``, beside
 this module) holds one entry per bucket of series length n and window

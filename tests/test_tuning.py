@@ -7,7 +7,7 @@ import json
 from paper_2304_01660_amd import tuning
 
 KEYS = {"dist_bits", "guard", "near_cols", "chunk_cols", "rows_near", "rows_far",
-        "rows_refine", "far_grid"}
+        "rows_refine", "far_grid", "band_pass"}
 
 
 def test_every_bucket_and_the_batch_hold_tuned_options():
