@@ -345,11 +345,14 @@ KernelTimer make_timer(palmad_ctx* ctx, const Opts& o)
     return t;
 }
 
-// After a synchronised round: add the device time of every kernel class.
+// After a synchronised round: add the device time of every kernel class
+// launched in it.
 int accumulate(palmad_ctx* ctx, KernelTimer& t)
 {
     if (!t.on) return PALMAD_OK;
     for (int k = 0; k < KCLASSES; ++k) {
+        if (!t.used[k]) continue;
+        t.used[k] = false;
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, t.ev[k][0], t.ev[k][1]));
         t.ms[k] += ms;

@@ -169,9 +169,13 @@ struct KernelTimer {
     hipEvent_t ev[KCLASSES][2];
     double ms[KCLASSES];
     unsigned long long launches[KCLASSES];
+    mutable bool used[KCLASSES];  // classes launched since the last accumulation
     void begin(int k, hipStream_t st) const
     {
-        if (on) (void)hipEventRecord(ev[k][0], st);
+        if (on) {
+            (void)hipEventRecord(ev[k][0], st);
+            used[k] = true;
+        }
     }
     void end(int k, hipStream_t st) const
     {

@@ -2696,9 +2696,6 @@ static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* t
         hipLaunchKernelGGL((k_select_band<F>), dim3((unsigned int)total[PFX_BAND]), dim3(64),
                            band_lds_bytes(bt.maxL_all, (int)sizeof(F)), st, bt.s, bt.B, bt.pfx[PFX_BAND]);
         cfg.timer->end(5, st);
-    } else {
-        cfg.timer->begin(5, st);
-        cfg.timer->end(5, st);
     }
     switch (cfg.q_near) {
     case 2: launch_near<F, 2>(bt, cfg, total, st); break;
@@ -2707,8 +2704,6 @@ static void launch_select(const Batch& bt, const SweepCfg& cfg, const int64_t* t
     }
     if ((int64_t)cfg.near_cols >= bt.Nmax_all) {
         // the first pass already covers every column of every series
-        cfg.timer->begin(1, st);
-        cfg.timer->end(1, st);
         return;
     }
     switch (cfg.q_far) {
