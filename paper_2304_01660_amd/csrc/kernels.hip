@@ -1840,6 +1840,27 @@ __device__ __forceinline__ Key wave_min_key(Key k)
 // the pooled per-wave lists.  In a direct round (no refinement sweep) every
 // live subsequence becomes a candidate.  Finally write the candidates'
 // centred windows x_k = t_{i+k} - mu_i and their sums for the exact pass.
+// fn(q, word) for every nonzero word q of the bitmap taken by this thread
+// (q = threadIdx.x + TOPK_BLOCK j): sixteen words are loaded before any is
+// scanned, so one memory latency covers them.
+template <typename Fn>
+__device__ __forceinline__ void scan_words(const unsigned long long* __restrict__ alive, int64_t nw,
+                                           Fn&& fn)
+{
+    constexpr int U = 16;
+    for (int64_t q0 = threadIdx.x; q0 < nw; q0 += (int64_t)U * TOPK_BLOCK) {
+        unsigned long long wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + (int64_t)u * TOPK_BLOCK;
+            wv[u] = q < nw ? alive[q] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (wv[u]) fn(q0 + (int64_t)u * TOPK_BLOCK, wv[u]);
+    }
+}
+
 __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
 {
     constexpr int NW = TOPK_BLOCK / 64;
@@ -1872,15 +1893,14 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
     if (direct_round(c)) {
         if (tid == 0) nc_s = 0;
         __syncthreads();
-        for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
-            unsigned long long bits = alive[q];
+        scan_words(alive, nw, [&](int64_t q, unsigned long long bits) {
             while (bits) {
                 const int t = __ffsll((long long)bits) - 1;
                 bits &= bits - 1ull;
                 const unsigned int slot = atomicAdd(&nc_s, 1u);
                 if (slot < (unsigned int)KP_MAX) cand_s[slot] = q * 64 + t;
             }
-        }
+        });
         __syncthreads();
         kp = (int)min(nc_s, (unsigned int)KP_MAX);
         if (kp < k) {
@@ -1897,7 +1917,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
         }
     } else {
         unsigned int cnt = 0;
-        for (int64_t q = tid; q < nw; q += TOPK_BLOCK) cnt += (unsigned int)__popcll(alive[q]);
+        scan_words(alive, nw, [&](int64_t, unsigned long long bits) { cnt += (unsigned int)__popcll(bits); });
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
         if (lane == 0) cnt_s[w] = cnt;
@@ -1917,17 +1937,15 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
             Key last = {0ull, -1};
             for (int r = 0; r < kp; ++r) {
                 Key best = {~0ull, KEY_NONE};
-                for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
-                    unsigned long long bits = alive[q];
+                scan_words(alive, nw, [&](int64_t q, unsigned long long bits) {
                     while (bits) {
                         const int t = __ffsll((long long)bits) - 1;
                         bits &= bits - 1ull;
                         const long long i = q * 64 + t;
                         const Key x = {key_of(i), i};
-                        if (r > 0 && !key_less(last, x)) continue;
-                        if (key_less(x, best)) best = x;
+                        if ((r == 0 || key_less(last, x)) && key_less(x, best)) best = x;
                     }
-                }
+                });
                 best = wave_min_key(best);
                 if (lane == 0) {
                     pu[w][r] = best.u;
@@ -1976,14 +1994,13 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
             if (tid == 0) nc_s = 0;
             __syncthreads();
             unsigned int nb = 0;
-            for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
-                unsigned long long bits = alive[q];
+            scan_words(alive, nw, [&](int64_t q, unsigned long long bits) {
                 while (bits) {
                     const int t = __ffsll((long long)bits) - 1;
                     bits &= bits - 1ull;
                     nb += key_of(q * 64 + t) <= ub ? 1u : 0u;
                 }
-            }
+            });
             if (nb) atomicAdd(&nc_s, nb);
             __syncthreads();
             const unsigned int nband = nc_s;
@@ -1999,8 +2016,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
             if (nband > (unsigned int)kp) {
                 if (tid == 0) nc_s = 0;
                 __syncthreads();
-                for (int64_t q = tid; q < nw; q += TOPK_BLOCK) {
-                    unsigned long long bits = alive[q];
+                scan_words(alive, nw, [&](int64_t q, unsigned long long bits) {
                     while (bits) {
                         const int t = __ffsll((long long)bits) - 1;
                         bits &= bits - 1ull;
@@ -2011,7 +2027,7 @@ __global__ __launch_bounds__(TOPK_BLOCK) void k_select_top(SeriesDev* S)
                             s.cand[slot] = i;
                         }
                     }
-                }
+                });
                 if (tid == 0) kp_s = (int)nband;
                 __syncthreads();
             }
