@@ -1602,10 +1602,11 @@ __global__ __launch_bounds__(64) void k_select_near(SeriesDev* S, int B,
 
 // Remaining selection work: items (live tile, chunk) drawn nearest-first
 // from each series' counter; a workgroup drains the series in rotated order.
+// The FP32 two-row tile fits 128 registers, so four waves share a SIMD
+// (three otherwise): the pass is bound by how many items are resident.
 template <typename F, int Q>
-__global__ __launch_bounds__(64) void k_select_far(SeriesDev* S, int B,
-                                                                        int near_cols, int chunk,
-                                                                        int near_rows)
+__global__ __launch_bounds__(64, (sizeof(F) == 4 && Q <= 2) ? 4 : 1) void k_select_far(
+    SeriesDev* S, int B, int near_cols, int chunk, int near_rows)
 {
     extern __shared__ double lds[];
     constexpr int R = 64 * Q;
