@@ -527,8 +527,14 @@ __device__ __forceinline__ void lds_fill(double* dst, const double* __restrict__
 // instruction (1024 multiply-adds) replace the two reads per multiply-add of
 // a vector loop, which left the sweeps bound by LDS bandwidth.
 typedef double pm_acc_t __attribute__((ext_vector_type(4)));
-constexpr int HK_PAD = 16;   // zeros before v (k - r >= -15)
-constexpr int BCOLS = 256;   // columns per boundary batch (one tile)
+constexpr int HK_PAD = 16;    // zeros before v (k - r >= -15)
+constexpr int HK_TILE = 256;  // values D(p) per Hankel tile
+// Columns per boundary batch: a whole tile for the FP32 sweeps; half a tile
+// for FP64 records, whose smaller staging lets more refinement items stay
+// resident (the FP32 sweeps measured slower at half a tile).
+__host__ __device__ constexpr int bcols_of(int fbytes) { return fbytes == 8 ? HK_TILE / 2 : HK_TILE; }
+template <typename F>
+__host__ __device__ constexpr int batch_cols() { return bcols_of((int)sizeof(F)); }
 // w is staged skewed (value p at p + p / 16), so that the 16 lanes reading
 // w[16 c + k] for c = 0..15 hit distinct LDS banks.
 __host__ __device__ constexpr int hk_skew(int p) { return p + (p >> 4); }
@@ -543,17 +549,20 @@ __device__ __forceinline__ int hk_offset(int q)
     return 16 * (lane & 15) + (lane >> 4) + 4 * q;
 }
 
-// D(p) for p < 256 (see above): vp = v after HK_PAD zeros, zero beyond m;
-// w = skewed LDS stretch starting at value wbase, at least wbase + 255 + m
-// + 16 values.  One accumulator (the matrix core chains dependent
+// D(p) for p < ncols (a multiple of 16, at most 256; see above): vp = v
+// after HK_PAD zeros, zero beyond m; w = skewed LDS stretch starting at value
+// wbase, at least wbase + ncols + m + 16 values.  Lanes of the columns
+// c >= ncols / 16 read the stretch's first column instead: their D values
+// are not meaningful.  One accumulator (the matrix core chains dependent
 // accumulations), so the sweep keeps its registers.
-__device__ __forceinline__ pm_acc_t hankel16(const double* vp, const double* w, int wbase, int m)
+__device__ __forceinline__ pm_acc_t hankel16(const double* vp, const double* w, int wbase, int m,
+                                             int ncols = HK_TILE)
 {
     const int lane = threadIdx.x;
     const int ca = lane & 15, ka = lane >> 4;
     const int K4 = hk_steps(m);
     const double* va = vp + HK_PAD + ka - ca;
-    const int wb = wbase + 16 * ca + ka;
+    const int wb = wbase + 16 * (16 * ca < ncols ? ca : 0) + ka;
     pm_acc_t d = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < K4; ++s)
         d = __builtin_amdgcn_mfma_f64_16x16x4f64(va[4 * s], w[hk_skew(wb + 4 * s)], d, 0, 0, 0);
@@ -580,7 +589,7 @@ __device__ __forceinline__ void stage_skewed(double* w, const double* __restrict
     }
 }
 
-// Column helpers of one step, staged in LDS per batch of BCOLS columns.
+// Column helpers of one step, staged in LDS per batch of columns.
 template <typename F>
 struct alignas(4 * sizeof(F)) H4 {
     F df, dg, inv;  // df[j-1], dg[j-1], 1/(sqrt(m) sigma_j)
@@ -594,19 +603,30 @@ struct alignas(4 * sizeof(F)) H4 {
 //   ws   [sweep_ws_doubles]  skewed series stretch: the rows' windows while
 //                            the first column is computed, then each batch's
 //                            columns
-//   hs   [BCOLS records]     per-step helpers and boundary values of a batch
+//   hs   [batch records]     per-step helpers and boundary values of a batch
 //                            (the first column's R row values before that)
 //   rowv [R]                 refinement only: per-row 1/(sqrt(m) sigma_i)
-__host__ __device__ constexpr int sweep_ws_count(int m, int R) { return (R > BCOLS ? R : BCOLS) + m + 16; }
-__host__ __device__ constexpr int sweep_ws_doubles(int m, int R)
+// (fbytes: bytes of the sweep's float type)
+__host__ __device__ constexpr int sweep_ws_count(int m, int R, int fbytes)
 {
-    return (hk_skew(sweep_ws_count(m, R) - 1) + 1 + 3) & ~3;
+    return (R > bcols_of(fbytes) ? R : bcols_of(fbytes)) + m + 16;
 }
-__host__ __device__ constexpr int sweep_hs_offset(int m, int R) { return hk_vp_doubles(m) + sweep_ws_doubles(m, R); }
-__host__ __device__ constexpr int sweep_hs_doubles(int fbytes) { return BCOLS * 4 * fbytes / 8; }
+__host__ __device__ constexpr int sweep_ws_doubles(int m, int R, int fbytes)
+{
+    return (hk_skew(sweep_ws_count(m, R, fbytes) - 1) + 1 + 3) & ~3;
+}
+__host__ __device__ constexpr int sweep_hs_offset(int m, int R, int fbytes)
+{
+    return hk_vp_doubles(m) + sweep_ws_doubles(m, R, fbytes);
+}
+// (the region first holds the R first-column values of an item, as doubles)
+__host__ __device__ constexpr int sweep_hs_doubles(int R, int fbytes)
+{
+    return bcols_of(fbytes) * 4 * fbytes / 8 > R ? bcols_of(fbytes) * 4 * fbytes / 8 : R;
+}
 __host__ __device__ constexpr int sweep_rowv_offset(int m, int R, int fbytes)
 {
-    return sweep_hs_offset(m, R) + sweep_hs_doubles(fbytes);
+    return sweep_hs_offset(m, R, fbytes) + sweep_hs_doubles(R, fbytes);
 }
 __host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, int fbytes, bool rowv)
 {
@@ -636,7 +656,7 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
         const int k = t - HK_PAD;
         xp[t] = (k >= 0 && k < m) ? T[jbeg + k] : 0.0;
     }
-    stage_skewed(ws, T + i0, sweep_ws_count(m, R));  // (tiles of 128 rows read 256 rows' worth)
+    stage_skewed(ws, T + i0, R + m + 16);
     __syncthreads();
     double sy = 0.0;
     for (int k = lane; k < m; k += 64) {
@@ -648,7 +668,7 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < (R + 255) / 256; ++h) {
-        const pm_acc_t D = hankel16(xp, ws, 256 * h, m);
+        const pm_acc_t D = hankel16(xp, ws, 256 * h, m, R - 256 * h < 256 ? R - 256 * h : 256);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int p = 256 * h + hk_offset(q);
@@ -669,12 +689,12 @@ __device__ void item_start(const double* __restrict__ T, const double* __restric
     __syncthreads();
 }
 
-// One batch of up to BCOLS columns from j0: the series stretch t[j0 ..
-// j0 + BCOLS + m + 16) staged skewed, then hs[p] = {df[j0+p-1], dg[j0+p-1],
+// One batch of up to NC columns from j0: the series stretch t[j0 ..
+// j0 + NC + m + 16) staged skewed, then hs[p] = {df[j0+p-1], dg[j0+p-1],
 // inv[j0+p], B(j0+p)} with the exact top-row values B(j) = sum_k x_k t_{j+k}
 // - mu_j Sx from one Hankel tile.  Reads stay inside the padded buffers
 // (their padding exceeds one 512-row tile beyond the last subsequence).
-template <typename F>
+template <typename F, int NC = batch_cols<F>()>
 __device__ void stage_batch(const double* __restrict__ T, const double* __restrict__ mu,
                             const F* __restrict__ df, const F* __restrict__ dg,
                             const F* __restrict__ inv, int32_t m, int64_t j0, const double* xp,
@@ -683,20 +703,20 @@ __device__ void stage_batch(const double* __restrict__ T, const double* __restri
     const int lane = threadIdx.x;
     __syncthreads();  // the previous batch is consumed
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NC / 64; ++u) {
         const int64_t j = j0 + lane + 64 * u;
         H4<F>& h = hs[lane + 64 * u];
         h.df = df[j - 1];
         h.dg = dg[j - 1];
         h.inv = inv[j];
     }
-    stage_skewed(ws, T + j0, BCOLS + m + 16);
+    stage_skewed(ws, T + j0, NC + m + 16);
     __syncthreads();
-    const pm_acc_t D = hankel16(xp, ws, 0, m);
+    const pm_acc_t D = hankel16(xp, ws, 0, m, NC);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int p = hk_offset(q);
-        hs[p].B = (F)(D[q] - mu[j0 + p] * Sx);
+        if (p < NC) hs[p].B = (F)(D[q] - mu[j0 + p] * Sx);
     }
     __syncthreads();
 }
@@ -944,7 +964,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     }
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R));
+    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R, (int)sizeof(F)));
     double Sx, Sy;
     F C[Q];
     {
@@ -988,11 +1008,11 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     uint32_t nblk = 0;
     int64_t j = jbeg + 1;
     while (go && j < jend) {
-        // a batch of up to BCOLS columns (one Hankel tile of boundary
-        // values), swept in blocks of 64 with the bitmap synchronised after
+        // a batch of up to batch_cols columns (boundary values from one
+        // Hankel tile), swept in blocks of 64 with the bitmap synchronised after
         // each
         stage_batch<F>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
-        const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+        const int64_t jb_end = std::min<int64_t>(jend, j + batch_cols<F>());
         for (int sb = 0; go && j < jb_end; ++sb) {
             const int nst = (int)std::min<int64_t>(64, jb_end - j);
             const H4<F>* hb = hs + 64 * sb;
@@ -1213,7 +1233,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     }
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R));
+    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R, (int)sizeof(double)));
     double Sx, Sy;
     double C[Q];
     item_start<Q>(A.T, A.mu, m, i0, jbeg, xp, ws, (double*)hs, Sx, Sy, C);
@@ -1245,7 +1265,7 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     bool go = true;
     while (go && j < jend) {
         stage_batch<double>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
-        const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+        const int64_t jb_end = std::min<int64_t>(jend, j + batch_cols<double>());
         for (int sb = 0; go && j < jb_end; ++sb) {
             const int nst = (int)std::min<int64_t>(64, jb_end - j);
             const H4<double>* hb = hs + 64 * sb;
@@ -1327,15 +1347,15 @@ constexpr int BAND_D = 64 * BAND_Q;      // diagonals per item
 constexpr int BAND_S = 256;              // rows per item (a multiple of 64)
 constexpr int BAND_C = BAND_S + BAND_D;  // column records per item (the last one is padding)
 constexpr int BAND_W32 = (BAND_C + 64) / 32;  // column-kill words, aligned to the bitmap
-static_assert(BAND_D == BCOLS, "one Hankel tile gives the top row's values");
+static_assert(BAND_D == HK_TILE, "one Hankel tile gives the top row's values");
 
 __host__ __device__ constexpr size_t band_lds_bytes(int m, int fbytes)
 {
     // phase 1: top-row window + skewed series stretch for the Hankel tile
     // phase 2: column records, row records, column-kill bits
-    return (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(BCOLS + m + 16 - 1) + 1 + 3) & ~3)) >
+    return (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(HK_TILE + m + 16 - 1) + 1 + 3) & ~3)) >
                    (size_t)4 * fbytes * (BAND_C + BAND_S) + 4 * BAND_W32
-               ? (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(BCOLS + m + 16 - 1) + 1 + 3) & ~3))
+               ? (size_t)8 * (hk_vp_doubles(m) + ((hk_skew(HK_TILE + m + 16 - 1) + 1 + 3) & ~3))
                : (size_t)4 * fbytes * (BAND_C + BAND_S) + 4 * BAND_W32;
 }
 
@@ -1417,7 +1437,7 @@ __global__ __launch_bounds__(64) void k_select_band(SeriesDev* S, int B, const i
             xp[t] = v;
         }
         const double Sx = wave_sum(sx);
-        stage_skewed(ws, A.T + j0, BCOLS + m + 16);
+        stage_skewed(ws, A.T + j0, HK_TILE + m + 16);
         __syncthreads();
         const pm_acc_t D = hankel16(xp, ws, 0, m);
         __syncthreads();  // the stretch is consumed: its space takes the values
@@ -2480,8 +2500,8 @@ __global__ __launch_bounds__(64) void k_drift(SeriesDev* S, int64_t nitems, int 
     const int lane = threadIdx.x;
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<double>* hs64 = (H4<double>*)(lds + sweep_hs_offset(m, R));
-    H4<float>* hs32 = (H4<float>*)(lds + sweep_hs_offset(m, R) + sweep_hs_doubles(8));
+    H4<double>* hs64 = (H4<double>*)(lds + sweep_hs_offset(m, R, 8));
+    H4<float>* hs32 = (H4<float>*)(lds + sweep_hs_offset(m, R, 8) + sweep_hs_doubles(R, 8));
     const int64_t ntiles = (N + R - 1) / R;
     // nitems <= 0: every (tile, chunk) of the right side, chunk-major
     const int64_t nchall = (N + chunk - 1) / chunk;
@@ -2518,9 +2538,11 @@ __global__ __launch_bounds__(64) void k_drift(SeriesDev* S, int64_t nitems, int 
             ri[q] = i;
         }
         for (int64_t j = jbeg + 1; j + Q <= jend; ) {
-            stage_batch<double>(A64.T, A64.mu, A64.df, A64.dg, A64.inv, m, j, xp, Sx, ws, hs64);
-            stage_batch<float>(A32.T, A32.mu, A32.df, A32.dg, A32.inv, m, j, xp, Sx, ws, hs32);
-            const int64_t jb_end = std::min<int64_t>(jend, j + BCOLS);
+            // both precisions in batches of the FP64 width
+            constexpr int NC = batch_cols<double>();
+            stage_batch<double, NC>(A64.T, A64.mu, A64.df, A64.dg, A64.inv, m, j, xp, Sx, ws, hs64);
+            stage_batch<float, NC>(A32.T, A32.mu, A32.df, A32.dg, A32.inv, m, j, xp, Sx, ws, hs32);
+            const int64_t jb_end = std::min<int64_t>(jend, j + NC);
             for (int s0 = 0; j + Q <= jb_end; s0 += Q, j += Q) {
 #define DRIFT_STEP(U)                                                                          \
     drift_step<U>(C32, C64, a32, b32, a64, b64, hs32[s0 + (U)], hs64[s0 + (U)], iv32, iv64, ri, \
@@ -2771,8 +2793,8 @@ hipError_t launch_drift(const Batch& bt, const int64_t* total, int32_t minL, int
     hipLaunchKernelGGL(k_guard, dim3(1), dim3(GUARD_BLOCK), 0, st, bt.s, guard);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)out, (int64_t)1,
                        0ull);
-    const size_t lds = sizeof(double) * (sweep_hs_offset(bt.maxL_all, 512) + sweep_hs_doubles(8) +
-                                         sweep_hs_doubles(4));
+    const size_t lds = sizeof(double) * (sweep_hs_offset(bt.maxL_all, 512, 8) + sweep_hs_doubles(512, 8) +
+                                         sweep_hs_doubles(0, 4));
     hipLaunchKernelGGL(k_drift, dim3(1024), dim3(64), lds, st, bt.s, nitems, chunk,
                        (unsigned long long*)out);
     hipLaunchKernelGGL(k_drift_band, dim3(1), dim3(1), 0, st, bt.s, guard, out);
