@@ -606,31 +606,32 @@ struct alignas(4 * sizeof(F)) H4 {
 //   hs   [batch records]     per-step helpers and boundary values of a batch
 //                            (the first column's R row values before that)
 //   rowv [R]                 refinement only: per-row 1/(sqrt(m) sigma_i)
-// (fbytes: bytes of the sweep's float type)
-__host__ __device__ constexpr int sweep_ws_count(int m, int R, int fbytes)
+// (fbytes: bytes of the sweep's float type; nc: columns per batch)
+__host__ __device__ constexpr int sweep_ws_count(int m, int R, int nc) { return (R > nc ? R : nc) + m + 16; }
+__host__ __device__ constexpr int sweep_ws_doubles(int m, int R, int nc)
 {
-    return (R > bcols_of(fbytes) ? R : bcols_of(fbytes)) + m + 16;
+    return (hk_skew(sweep_ws_count(m, R, nc) - 1) + 1 + 3) & ~3;
 }
-__host__ __device__ constexpr int sweep_ws_doubles(int m, int R, int fbytes)
+__host__ __device__ constexpr int sweep_hs_offset(int m, int R, int nc)
 {
-    return (hk_skew(sweep_ws_count(m, R, fbytes) - 1) + 1 + 3) & ~3;
-}
-__host__ __device__ constexpr int sweep_hs_offset(int m, int R, int fbytes)
-{
-    return hk_vp_doubles(m) + sweep_ws_doubles(m, R, fbytes);
+    return hk_vp_doubles(m) + sweep_ws_doubles(m, R, nc);
 }
 // (the region first holds the R first-column values of an item, as doubles)
-__host__ __device__ constexpr int sweep_hs_doubles(int R, int fbytes)
+__host__ __device__ constexpr int sweep_hs_doubles(int R, int fbytes, int nc)
 {
-    return bcols_of(fbytes) * 4 * fbytes / 8 > R ? bcols_of(fbytes) * 4 * fbytes / 8 : R;
+    return nc * 4 * fbytes / 8 > R ? nc * 4 * fbytes / 8 : R;
 }
-__host__ __device__ constexpr int sweep_rowv_offset(int m, int R, int fbytes)
+__host__ __device__ constexpr int sweep_rowv_offset(int m, int R, int fbytes, int nc)
 {
-    return sweep_hs_offset(m, R, fbytes) + sweep_hs_doubles(R, fbytes);
+    return sweep_hs_offset(m, R, nc) + sweep_hs_doubles(R, fbytes, nc);
+}
+__host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, int fbytes, bool rowv, int nc)
+{
+    return (size_t)(sweep_rowv_offset(m, R, fbytes, nc) + (rowv ? R : 0));
 }
 __host__ __device__ constexpr size_t sweep_lds_doubles(int m, int R, int fbytes, bool rowv)
 {
-    return (size_t)(sweep_rowv_offset(m, R, fbytes) + (rowv ? R : 0));
+    return sweep_lds_doubles(m, R, fbytes, rowv, bcols_of(fbytes));
 }
 
 // Start of a sweep work item (one wavefront, row tile of R = 64 Q rows from
@@ -964,7 +965,7 @@ __device__ void sel_item(const SweepArgs<F>& A, int64_t i0, int64_t jbeg, int64_
     }
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R, (int)sizeof(F)));
+    H4<F>* hs = (H4<F>*)(lds + sweep_hs_offset(m, R, batch_cols<F>()));
     double Sx, Sy;
     F C[Q];
     {
@@ -1209,7 +1210,7 @@ __device__ __forceinline__ void ref_block_full(double (&C)[Q], const double (&a)
     }
 }
 
-template <int Q>
+template <int Q, int NC = batch_cols<double>()>
 __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, int64_t jend,
                          bool left, double thr, int prune, double* lds, unsigned long long& evals)
 {
@@ -1233,14 +1234,14 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     }
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R, (int)sizeof(double)));
+    H4<double>* hs = (H4<double>*)(lds + sweep_hs_offset(m, R, NC));
     double Sx, Sy;
     double C[Q];
     item_start<Q>(A.T, A.mu, m, i0, jbeg, xp, ws, (double*)hs, Sx, Sy, C);
     double a[Q], b[Q], mx[Q];
     int32_t ri[Q];
     // 1/(sqrt(m) sigma_i) of the lane's rows
-    double* rowinv = lds + sweep_rowv_offset(m, R, (int)sizeof(double));
+    double* rowinv = lds + sweep_rowv_offset(m, R, 8, NC);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int64_t i = rbase + q;
@@ -1264,8 +1265,8 @@ __device__ void ref_item(const SweepArgs<double>& A, int64_t i0, int64_t jbeg, i
     int64_t j = jbeg + 1;
     bool go = true;
     while (go && j < jend) {
-        stage_batch<double>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
-        const int64_t jb_end = std::min<int64_t>(jend, j + batch_cols<double>());
+        stage_batch<double, NC>(A.T, A.mu, A.df, A.dg, A.inv, m, j, xp, Sx, ws, hs);
+        const int64_t jb_end = std::min<int64_t>(jend, j + NC);
         for (int sb = 0; go && j < jb_end; ++sb) {
             const int nst = (int)std::min<int64_t>(64, jb_end - j);
             const H4<double>* hb = hs + 64 * sb;
@@ -2500,8 +2501,9 @@ __global__ __launch_bounds__(64) void k_drift(SeriesDev* S, int64_t nitems, int 
     const int lane = threadIdx.x;
     double* xp = lds;
     double* ws = lds + hk_vp_doubles(m);
-    H4<double>* hs64 = (H4<double>*)(lds + sweep_hs_offset(m, R, 8));
-    H4<float>* hs32 = (H4<float>*)(lds + sweep_hs_offset(m, R, 8) + sweep_hs_doubles(R, 8));
+    constexpr int NC = batch_cols<double>();  // both precisions in batches of the FP64 width
+    H4<double>* hs64 = (H4<double>*)(lds + sweep_hs_offset(m, R, NC));
+    H4<float>* hs32 = (H4<float>*)(lds + sweep_hs_offset(m, R, NC) + sweep_hs_doubles(R, 8, NC));
     const int64_t ntiles = (N + R - 1) / R;
     // nitems <= 0: every (tile, chunk) of the right side, chunk-major
     const int64_t nchall = (N + chunk - 1) / chunk;
@@ -2538,8 +2540,6 @@ __global__ __launch_bounds__(64) void k_drift(SeriesDev* S, int64_t nitems, int 
             ri[q] = i;
         }
         for (int64_t j = jbeg + 1; j + Q <= jend; ) {
-            // both precisions in batches of the FP64 width
-            constexpr int NC = batch_cols<double>();
             stage_batch<double, NC>(A64.T, A64.mu, A64.df, A64.dg, A64.inv, m, j, xp, Sx, ws, hs64);
             stage_batch<float, NC>(A32.T, A32.mu, A32.df, A32.dg, A32.inv, m, j, xp, Sx, ws, hs32);
             const int64_t jb_end = std::min<int64_t>(jend, j + NC);
@@ -2630,7 +2630,7 @@ __global__ __launch_bounds__(64, (Q <= 4 ? 3 : 1)) void k_stream_band(SeriesDev*
             jend = std::min<int64_t>(N, jbeg + chunk);
         }
         if (jbeg >= jend) continue;
-        ref_item<Q>(A, i0, jbeg, jend, left, 2.0, 0, lds, ev);
+        ref_item<Q, HK_TILE>(A, i0, jbeg, jend, left, 2.0, 0, lds, ev);
     }
     if (threadIdx.x == 0 && ev)
         atomicAdd(&s.evc[EV_REF * EV_SLOTS + (blockIdx.x & (EV_SLOTS - 1))], ev);
@@ -2793,8 +2793,9 @@ hipError_t launch_drift(const Batch& bt, const int64_t* total, int32_t minL, int
     hipLaunchKernelGGL(k_guard, dim3(1), dim3(GUARD_BLOCK), 0, st, bt.s, guard);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)out, (int64_t)1,
                        0ull);
-    const size_t lds = sizeof(double) * (sweep_hs_offset(bt.maxL_all, 512, 8) + sweep_hs_doubles(512, 8) +
-                                         sweep_hs_doubles(0, 4));
+    constexpr int NC = batch_cols<double>();
+    const size_t lds = sizeof(double) * (sweep_hs_offset(bt.maxL_all, 512, NC) + sweep_hs_doubles(512, 8, NC) +
+                                         sweep_hs_doubles(0, 4, NC));
     hipLaunchKernelGGL(k_drift, dim3(1024), dim3(64), lds, st, bt.s, nitems, chunk,
                        (unsigned long long*)out);
     hipLaunchKernelGGL(k_drift_band, dim3(1), dim3(1), 0, st, bt.s, guard, out);
@@ -2808,7 +2809,7 @@ template <int Q>
 static void launch_band(const Batch& bt, const SweepCfg& cfg, unsigned long long* prof,
                         int64_t n_old, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(double), true);
+    const size_t lds = sizeof(double) * sweep_lds_doubles(bt.maxL_all, 64 * Q, (int)sizeof(double), true, HK_TILE);
     hipLaunchKernelGGL((k_stream_band<Q>), dim3(cfg.far_grid), dim3(64), lds, st, bt.s, prof, n_old,
                        cfg.chunk_cols);
 }
