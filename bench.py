@@ -463,19 +463,29 @@ def stream_leg(api, torch, dev, w, cuts, reps: int = 2):
     }
 
 
+def kernel_build_flags() -> list:
+    """The hipcc flags the library's kernels are built with."""
+    import __graft_entry__ as ge
+
+    return [f for f in ge.HIP_FLAGS if f not in ("-shared", "-I", os.path.join(ROOT, "include"))] + \
+        list(ge.SOURCES["kernels.hip"])
+
+
 def measured_traffic(kernel: str, workload: str, options: dict):
     """HBM bytes per launch of `kernel` from the stored hardware-counter
     summary under profiles/, if it was taken on this exact kernel source,
-    workload and tile geometry (None otherwise)."""
+    build flags, workload and tile geometry (None otherwise)."""
     import glob
     import hashlib
 
     src = os.path.join(ROOT, "paper_2304_01660_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    flags = kernel_build_flags()
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         rec = json.load(open(path))
         if (rec.get("kernel") == kernel and rec.get("workload") == workload
-                and rec.get("tile_options") == options and rec.get("kernels_hip_sha256") == sha):
+                and rec.get("tile_options") == options and rec.get("kernels_hip_sha256") == sha
+                and rec.get("build_flags") == flags):
             return rec["bytes_per_launch"], os.path.relpath(path, ROOT)
     return None, None
 

@@ -1,4 +1,5 @@
-"""The HIP sources are built without packed FP32 instructions.
+"""The HIP sources are built without packed FP32 instructions, and their
+kernels make no function calls.
 
 The build passes the target feature that disables them to hipcc.  The host
 compilation passes print a warning that they do not know the feature; the
@@ -6,6 +7,11 @@ device pass does honour it.  This test compiles a small float2 kernel both
 ways to show that the flag removes packed FP32 arithmetic, then compiles
 every library source to gfx950 assembly with the build's own flags and
 checks that none contains a packed FP32 add, multiply or fused multiply-add.
+The same assembly must hold no call: the device library's work-item and
+work-group queries are inlined only when the kernels share its floating-point
+mode attributes (building with the IEEE mode bit off turned each of them into
+a call, and the call's register convention into extra registers in every
+kernel).
 """
 
 import os
@@ -22,6 +28,7 @@ sys.path.insert(0, ROOT)
 import __graft_entry__ as ge  # noqa: E402
 
 PACKED = re.compile(r"\bv_pk_(add|mul|fma)_f32\b")
+CALL = re.compile(r"\bs_(swappc|setpc)_b64\b")
 TOY = """#include <hip/hip_runtime.h>
 __global__ void k(float2* a, const float2* b, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -56,8 +63,10 @@ def test_flag_removes_packed_fp32_from_a_float2_kernel():
 
 
 @pytest.mark.parametrize("src", sorted(ge.SOURCES))
-def test_library_sources_have_no_packed_fp32(src):
+def test_library_sources_have_no_packed_fp32_and_no_calls(src):
     with tempfile.TemporaryDirectory() as d:
         asm = _device_asm(os.path.join(ge.CSRC, src), _flags(ge.SOURCES[src]), d)
         hits = sorted(set(m.group(0) for m in PACKED.finditer(asm)))
         assert not hits, (src, hits)
+        calls = sorted(set(m.group(0) for m in CALL.finditer(asm)))
+        assert not calls, (src, calls)
